@@ -1,0 +1,279 @@
+"""Benchmark: Gpixel/s and % of the HBM roofline, batched vs plain, plus
+p50/p99 latency of the served stream, on one MI355X.
+
+One step = one replay of the batch plan over the 512-image batch (seeded
+synthetic FP32 images, widths and heights log-uniform in [64, 2048], radius
+1..4, Gaussian sigma in [0.5, 2.0); the 2D and separable tile bodies chosen
+per image by the tune table), a single persistent launch captured in a
+hipGraph. `value` is output Gpixel/s over the timed steps.
+
+Printed as one JSON line with, besides the contract fields:
+  roofline      the batch kernel's algorithmic bytes (8 per pixel) over its
+                average duration from HIP events on its stream, against
+                8 TB/s; `traffic` is filled from committed counter profiles
+                when they match the current kernel, else null;
+  plain         the same 512 images as 512 single-image launches;
+  large_2d / large_sep   the 4096x4096 5x5 Gaussian (2D and fused
+                separable), buffers rotated over 1 GiB;
+  rgb_u8        1920x1080 planar RGB 7x7 integer filter;
+  serve         open-loop Poisson arrivals at 2000 req/s (p50/p99/p99.9);
+  cpu_baseline  the C oracle on one host core over a sample of the batch.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: dot4 lane-ops/s
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--cpu-sample-stride", type=int, default=16)
+    ap.add_argument("--tune", default=os.path.join(ROOT, "paper_1302_5586_amd", "tune_mi355x.json"))
+    ap.add_argument("--skip", default="", help="comma list of sections to skip: plain,large,rgb,serve,cpu")
+    return ap.parse_args()
+
+
+def time_events(torch, fn, reps, stream):
+    """Average ms per call from HIP events recorded on `stream` around
+    `reps` back-to-back calls."""
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for i in range(reps):
+        fn(i)
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); multi-GPU sharding is design-only",
+              file=sys.stderr)
+        sys.exit(2)
+    skip = set(s for s in args.skip.split(",") if s)
+
+    import torch
+
+    import paper_1302_5586_amd as pf
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pf.load()
+    stream = torch.cuda.current_stream()
+    if os.path.exists(args.tune):
+        pf.tune_load(args.tune)
+        log("tune table: %s" % args.tune)
+
+    # ---- batch workload (512 images, seed 3) --------------------------------
+    t0 = time.time()
+    b = synth.config_batch()
+    kinds = [pf.KIND_SEP] * b.n
+    filters = [np.concatenate([b.fx[i], b.fx[i]]) for i in range(b.n)]
+    pk = pf.pack_batch(b.images, filters, kinds)
+    log("batch generated: %d images, %d px (%.1f s)" % (b.n, b.pixels, time.time() - t0))
+    x = torch.from_numpy(pk.pixels).to(dev)
+    fl = torch.from_numpy(pk.filters).to(dev)
+    out = torch.empty_like(x)
+    plan = pf.BatchPlan(pk.h, pk.w, pk.r, pk.kind, pk.pix_off, pk.filt_off, x.numel(), fl.numel(), graph=True)
+    info = plan.info()
+    variants = plan.variants()
+    px = b.pixels
+    alg_bytes = 8 * px
+
+    for _ in range(args.warmup):
+        plan.run(x, fl, out)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record(stream)
+        plan.run(x, fl, out)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    kms = [e0.elapsed_time(e1) for e0, e1 in ev]
+    k_avg_ms = float(np.mean(kms))
+    ms_per_step = wall * 1000.0 / args.steps
+    value = px * args.steps / wall / 1e9
+    achieved = alg_bytes / (k_avg_ms * 1e-3) / 1e9
+    log("batched: %.3f ms/step wall, kernel avg %.3f ms, %.1f Gpx/s, %.0f GB/s" % (ms_per_step, k_avg_ms, value, achieved))
+
+    result = {
+        "metric": "Gpixel/s + % HBM roofline, batched vs plain; p50/p99 request latency",
+        "value": round(value, 3),
+        "unit": "Gpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded numpy PCG64 images; no dataset)",
+        "config": {"workload": "batch of 512 FP32 images, sizes log-uniform 64..2048, r 1..4, Gaussian sigma "
+                               "0.5..2.0, seed 3; one persistent launch replayed from a hipGraph",
+                   "images": b.n, "pixels": px, "wave_tiles": info["tasks"], "grid": info["grid"],
+                   "launches_per_step": info["launches"],
+                   "variants": {name: int((variants == v).sum()) for v, name in
+                                ((0, "direct"), (1, "separable"), (2, "separable_as_2d"))}},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_batch_f32", "algorithmic_bytes_per_launch": alg_bytes,
+                     "avg_kernel_ms": round(k_avg_ms, 4)},
+    }
+
+    # ---- plain: the same images as single-image launches ---------------------
+    if "plain" not in skip:
+        offs = pk.pix_off
+        f_off = pk.filt_off
+        views = []
+        for i in range(b.n):
+            n = int(pk.h[i]) * int(pk.w[i])
+            k = 2 * int(pk.r[i]) + 1
+            xi = x[offs[i]:offs[i] + n].view(int(pk.h[i]), int(pk.w[i]))
+            oi = out[offs[i]:offs[i] + n].view(int(pk.h[i]), int(pk.w[i]))
+            fx = fl[f_off[i]:f_off[i] + k]
+            fy = fl[f_off[i] + k:f_off[i] + 2 * k]
+            views.append((xi, fx, fy, oi))
+
+        def plain_step(_):
+            for xi, fx, fy, oi in views:
+                pf.filter_sep(xi, fx, fy, out=oi)
+
+        plain_step(0)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        ms = time_events(torch, plain_step, max(3, args.steps // 4), stream)
+        torch.cuda.synchronize()
+        pv = px / (ms * 1e-3) / 1e9
+        result["plain"] = {"value": round(pv, 3), "unit": "Gpixel/s", "ms_per_step": round(ms, 4),
+                           "launches_per_step": b.n, "batched_speedup": round(value / pv, 3)}
+        log("plain: %.3f ms/step, %.1f Gpx/s (batched x%.2f)" % (ms, pv, value / pv))
+
+    # ---- 4096x4096 5x5 Gaussian, plain filter ---------------------------------
+    if "large" not in skip:
+        cfg = synth.config_large()
+        n = cfg.h * cfg.w
+        nbuf = 8   # 8 x 128 MiB of in+out: the 256 MB last-level cache cannot serve it
+        xs = [torch.from_numpy(cfg.image).to(dev) for _ in range(nbuf)]
+        os_ = [torch.empty_like(xs[0]) for _ in range(nbuf)]
+        f2 = torch.from_numpy(cfg.f2d).to(dev)
+        g1 = torch.from_numpy(cfg.f1d).to(dev)
+        g2 = g1.clone()
+        for name, fn in (("large_2d", lambda i: pf.filter2d(xs[i % nbuf], f2, out=os_[i % nbuf])),
+                         ("large_sep", lambda i: pf.filter_sep(xs[i % nbuf], g1, g2, out=os_[i % nbuf]))):
+            for i in range(nbuf):
+                fn(i)
+            ms = time_events(torch, fn, 64, stream)
+            gbs = 8 * n / (ms * 1e-3) / 1e9
+            result[name] = {"value": round(n / (ms * 1e-3) / 1e9, 3), "unit": "Gpixel/s", "us_per_call": round(ms * 1e3, 2),
+                            "achieved_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                            "workload": "4096x4096 FP32, 5x5 Gaussian sigma 1.5, seed 1, buffers rotated over 1 GiB"}
+            log("%s: %.2f us/call, %.0f GB/s (%.1f%% of HBM)" % (name, ms * 1e3, gbs, 100 * gbs / HBM_PEAK_GBS))
+        del xs, os_
+
+    # ---- 1080p RGB uint8 7x7 -------------------------------------------------
+    if "rgb" not in skip:
+        cfg = synth.config_rgb()
+        xu = torch.from_numpy(cfg.image).to(dev)
+        ou = torch.empty_like(xu)
+        fu = torch.from_numpy(cfg.filt).to(dev)
+        fn = lambda i: pf.filter2d_u8(xu, fu, cfg.shift, out=ou)  # noqa: E731
+        fn(0)
+        ms = time_events(torch, fn, 200, stream)
+        npx = cfg.c * cfg.h * cfg.w
+        dot4 = npx * (2 * cfg.r + 1) * ((2 * cfg.r + 1 + 3) // 4)
+        result["rgb_u8"] = {"value": round(npx / (ms * 1e-3) / 1e9, 3), "unit": "Gpixel/s (pixels x channels)",
+                            "us_per_call": round(ms * 1e3, 2),
+                            "achieved_GBs": round(2 * npx / (ms * 1e-3) / 1e9, 1),
+                            "dot4_lane_ops_per_s": round(dot4 / (ms * 1e-3) / 1e12, 3),
+                            "frac_alu_dot4": round(dot4 / (ms * 1e-3) / VALU_LANE_OPS, 4),
+                            "workload": "3x1080x1920 uint8 planar, 7x7 int8 weights in -8..8, shift 6, seed 2"}
+        log("rgb_u8: %.2f us/call" % (ms * 1e3))
+
+    # ---- serving ------------------------------------------------------------
+    if "serve" not in skip and args.serve_seconds > 0:
+        tr = synth.arrival_trace(rate=args.serve_rate, duration=args.serve_seconds)
+        pool = synth.serve_pool()
+        offs = np.zeros(pool.n, np.int64)
+        o = 0
+        for i in range(pool.n):
+            offs[i] = o
+            o += int(pool.h[i] * pool.w[i])
+            o = (o + 63) // 64 * 64
+        arena = np.zeros(o, np.float32)
+        for i in range(pool.n):
+            arena[offs[i]:offs[i] + pool.images[i].size] = pool.images[i].ravel()
+        pool_dev = torch.from_numpy(arena).to(dev)
+        del arena
+        # per-request Gaussian fx = fy, packed on the host
+        fls, foffs = [], np.zeros(tr.n, np.int64)
+        fo = 0
+        for i in range(tr.n):
+            g = synth.gaussian_1d(int(tr.r[i]), float(tr.sigma[i]))
+            fls.append(g)
+            fls.append(g)
+            foffs[i] = fo
+            fo += 2 * g.size
+        flt = np.concatenate(fls)
+        pi = tr.pool_index
+        hh, ww = pool.h[pi], pool.w[pi]
+        log("serve: %d requests over %.0f s at %.0f req/s" % (tr.n, args.serve_seconds, args.serve_rate))
+        srv = pf.Server(64 << 30, n_streams=4, max_batch=64, max_queue=1 << 20)
+        st = srv.run_trace((tr.t * 1e9).astype(np.int64), hh, ww, tr.r, offs[pi], foffs, pool_dev, flt)
+        srv.close()
+        result["serve"] = {"requests": tr.n, "rate_req_s": args.serve_rate, "seconds": args.serve_seconds,
+                           "p50_us": round(st["p50_us"], 1), "p99_us": round(st["p99_us"], 1),
+                           "p999_us": round(st["p999_us"], 1), "max_us": round(st["max_us"], 1),
+                           "gpx_per_s": round(st["gpx_per_s"], 4), "batches": st["batches"],
+                           "mean_batch": round(st["mean_batch"], 2), "budget_bytes": 64 << 30,
+                           "workload": "open-loop Poisson arrivals, seed 4; device-resident pool of 1024 images "
+                                       "(seed 40) sized as the batch; r 1..4; separable Gaussians"}
+        log("serve: p50 %.1f us p99 %.1f us, %.3f Gpx/s, mean batch %.2f" % (st["p50_us"], st["p99_us"],
+                                                                          st["gpx_per_s"], st["mean_batch"]))
+
+    # ---- CPU baseline: the oracle on one core over a sample -------------------
+    if "cpu" not in skip:
+        import oracle
+        sample = list(range(0, b.n, args.cpu_sample_stride))
+        spx = 0
+        c0 = time.perf_counter()
+        for i in sample:
+            oracle.filter_sep_f32(b.images[i], b.fx[i], b.fx[i])
+            spx += b.images[i].size
+        cs = time.perf_counter() - c0
+        result["cpu_baseline"] = {"value": round(spx / cs / 1e9, 5), "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
+                                  "sample": "every %dth image of the 512-image batch (%d images, %d px), separable "
+                                            "oracle, %.1f s" % (args.cpu_sample_stride, len(sample), spx, cs)}
+        log("cpu oracle: %.4f Gpx/s on one core (%.1f s)" % (spx / cs / 1e9, cs))
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

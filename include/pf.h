@@ -1,0 +1,273 @@
+/*
+ * pf.h -- C ABI of the MI355X (gfx950) clamp-to-edge image filter library
+ * (libpencilfilter.so).
+ *
+ * Shape of every call, after the paper's coding rules for a PENCIL function
+ * (Sec. II-B.1): sizes come first, then arrays declared as C99 VLAs qualified
+ * `restrict const static` (distinct arrays never overlap, each holds at least
+ * the stated number of elements), then scalar out-parameters as
+ * `T *const restrict`. Batches are described without arrays of pointers: one
+ * arena per kind of data plus per-item offsets, the (array, index) form the
+ * paper gives for OP2's rewritten kernel (Sec. III-A). Semantics are those of
+ * the sequential loop nest, whose output iterations are independent
+ * (Sec. II-B.3), so the library computes them in any order.
+ *
+ * Filter semantics (all entry points): correlation without kernel flip,
+ *     out[y][x] = sum_{dy=-r..r} sum_{dx=-r..r} f[dy+r][dx+r] * in[cy][cx],
+ *     cy = clamp(y+dy, 0, h-1),  cx = clamp(x+dx, 0, w-1)
+ * with row-major dense images (pitch = w) and row-major filters. The
+ * separable form computes the row pass with fx (horizontal taps) into an
+ * FP32 intermediate and then the column pass with fy (vertical taps).
+ *
+ * Memory: unless stated otherwise, every array argument is a DEVICE pointer
+ * (HIP device memory of the current device, e.g. a torch tensor's
+ * data_ptr()). `stream` is a hipStream_t passed as void*; NULL is the null
+ * stream. The caller owns every buffer it passes. Filter calls are
+ * asynchronous on `stream`: they return after enqueueing, and their buffers
+ * must stay alive and unmodified until the stream reaches the work. The
+ * library keeps no pointer to caller memory after the call returns (batch
+ * plans keep none beyond a run either).
+ *
+ * Errors: no exception crosses the ABI. Every call returns a pf_status;
+ * pf_last_error() gives a thread-local message for the last failing call on
+ * the calling thread. Arguments are validated before anything is enqueued;
+ * an invalid call enqueues nothing. Asynchronous device faults surface on a
+ * later synchronising call as PF_EDEVICE.
+ *
+ * Precision: FP32 results agree with the sequential definition within the
+ * FP32 inner-product bound (taps may be fused multiply-adds, summed in the
+ * definition's order dy outer, dx inner). With PF_FLAG_EXACT the FP32 paths
+ * use a separate multiply and add per tap in that same order, and reproduce
+ * the sequential C program bit for bit. The integer path is exact.
+ */
+#ifndef PENCILFILTER_PF_H
+#define PENCILFILTER_PF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+/* C++ sees each VLA parameter as a restrict-qualified pointer. */
+#define PF_ARR(T, name, n) T *__restrict name
+#define PF_OUTP(T, name) T *const __restrict name
+#else
+#define PF_ARR(T, name, n) T name[restrict const static (n)]
+#define PF_OUTP(T, name) T *const restrict name
+#endif
+
+/* ---- status ------------------------------------------------------------- */
+typedef int32_t pf_status;
+#define PF_OK            0  /* success                                        */
+#define PF_EINVAL        1  /* bad size, radius, null pointer, bad flag       */
+#define PF_EALIAS        2  /* input and output ranges overlap (restrict)     */
+#define PF_EUNSUPPORTED  3  /* valid C, but outside what this build supports */
+#define PF_EDEVICE       4  /* HIP runtime or device error                    */
+#define PF_ENOMEM        5  /* host or device allocation failed               */
+#define PF_EBUDGET       6  /* request larger than the whole HBM budget       */
+#define PF_EAGAIN        7  /* queue full or result not ready; try again      */
+#define PF_ETIMEDOUT     8  /* wait ended before completion                   */
+
+/* Largest supported filter radius (filters up to 17 x 17). */
+#define PF_R_MAX 8
+
+/* Flags for single-image calls, batch plans and servers. */
+#define PF_FLAG_EXACT       0x1  /* separate FP32 mul and add per tap, definition order */
+#define PF_BATCH_GRAPH      0x2  /* batch plan: capture its launches in a hipGraph      */
+#define PF_BATCH_NO_TUNE    0x4  /* batch plan: ignore the tune table, use defaults     */
+
+/* Filter kinds inside a batch or a served request (and tune-table keys). */
+#define PF_KIND_2D   0  /* (2r+1)^2 weights, row-major, at filt_off               */
+#define PF_KIND_SEP  1  /* fx[2r+1] at filt_off, then fy[2r+1] right after it     */
+#define PF_KIND_U8   2  /* tune-table key of the uint8 path (not a batch kind)    */
+
+/* Execution variants a kind may run as (chosen by the tune table). */
+#define PF_VAR_DIRECT      0  /* full 2D taps                                     */
+#define PF_VAR_SEPARABLE   1  /* fused row pass + column pass (PF_KIND_SEP only)  */
+#define PF_VAR_SEP_DIRECT  2  /* PF_KIND_SEP run as 2D taps fy[i]*fx[j] (FP32)    */
+
+const char *pf_status_str(pf_status s);
+/* Message of the last failing call on this thread ("" if none). The string
+ * stays valid until the next pf_* call on the same thread. */
+const char *pf_last_error(void);
+/* Library version string, and the gfx target the kernels were built for. */
+const char *pf_version(void);
+
+/* ---- single image: FP32 full 2D -----------------------------------------
+ * Sec. II (stencils as regular, statically analysable loop nests) and
+ * Sec. II-B.1 (calling convention). h, w >= 1; 0 <= r <= PF_R_MAX.
+ * in, out: float[h*w] device, 4-byte aligned, disjoint (else PF_EALIAS).
+ * filt: float[(2r+1)^2] device. flags: 0 or PF_FLAG_EXACT. */
+pf_status pf_filter2d_f32(int32_t h, int32_t w, int32_t r,
+                          PF_ARR(const float, in, h * w),
+                          PF_ARR(const float, filt, (2 * r + 1) * (2 * r + 1)),
+                          PF_ARR(float, out, h * w),
+                          int32_t flags, void *stream);
+
+/* ---- single image: FP32 separable ---------------------------------------
+ * Row pass with fx, FP32 intermediate, column pass with fy, fused in one
+ * kernel: the intermediate never reaches memory (the cross-kernel fusion
+ * that Sec. II's cross-component optimisation motivates). Same rules as
+ * pf_filter2d_f32; fx and fy: float[2r+1] device. */
+pf_status pf_filter_sep_f32(int32_t h, int32_t w, int32_t r,
+                            PF_ARR(const float, in, h * w),
+                            PF_ARR(const float, fx, 2 * r + 1),
+                            PF_ARR(const float, fy, 2 * r + 1),
+                            PF_ARR(float, out, h * w),
+                            int32_t flags, void *stream);
+
+/* ---- single image: uint8 planar, integer ----------------------------------
+ * c planes of h x w uint8 (plane p at offset p*h*w), one int8 filter for
+ * all planes: acc = sum of int8 weight * uint8 pixel in int32 (exact),
+ * q = acc >> shift (arithmetic, i.e. floor), out = min(max(q, 0), 255).
+ * c, h, w >= 1; 0 <= r <= PF_R_MAX; 0 <= shift <= 31. in and out disjoint.
+ * filt: int8[(2r+1)^2] device. flags must be 0. */
+pf_status pf_filter2d_u8(int32_t c, int32_t h, int32_t w, int32_t r, int32_t shift,
+                         PF_ARR(const uint8_t, in, c * h * w),
+                         PF_ARR(const int8_t, filt, (2 * r + 1) * (2 * r + 1)),
+                         PF_ARR(uint8_t, out, c * h * w),
+                         int32_t flags, void *stream);
+
+/* ---- single image with an explicit launch shape ----------------------------
+ * The same computation as the call for `kind`/`variant`, with the launch
+ * shape forced: rows_per_wave in {4, 8, 16, 32, 64, 128}, waves_per_group in
+ * {1, 2, 4, 8}. Used by the autotuner and by tests that check results do
+ * not depend on the launch shape. kind PF_KIND_2D requires variant
+ * PF_VAR_DIRECT; PF_KIND_SEP accepts all three variants. For PF_KIND_SEP,
+ * filt holds fx then fy (2*(2r+1) floats). */
+pf_status pf_filter_f32_shaped(int32_t h, int32_t w, int32_t r, int32_t kind, int32_t variant,
+                               int32_t rows_per_wave, int32_t waves_per_group,
+                               PF_ARR(const float, in, h * w),
+                               const float *filt,
+                               PF_ARR(float, out, h * w),
+                               int32_t flags, void *stream);
+
+/* ---- tuning (profile-based auto-tuning, Sec. II, Fig. 1 flow) -------------
+ * The tune table maps (kind, r, size class) to a variant and a launch
+ * shape. Size classes: 0 small (< 256*256 px), 1 medium, 2 large
+ * (> 1024*1024 px). A built-in default table is used until one is loaded. */
+typedef struct pf_tune_entry {
+    int32_t kind;             /* PF_KIND_2D, PF_KIND_SEP, PF_KIND_U8 */
+    int32_t r;                /* 0..PF_R_MAX                   */
+    int32_t size_class;       /* 0, 1, 2                       */
+    int32_t variant;          /* PF_VAR_*                      */
+    int32_t rows_per_wave;
+    int32_t waves_per_group;
+    float   us;               /* measured median time, or 0    */
+} pf_tune_entry;
+
+pf_status pf_tune_lookup(int32_t kind, int32_t r, int64_t pixels, PF_OUTP(pf_tune_entry, e));
+/* Replace the active table with n entries (missing keys keep defaults). */
+pf_status pf_tune_set(int32_t n, PF_ARR(const pf_tune_entry, entries, n));
+pf_status pf_tune_reset(void);
+/* Load / save the table as JSON text (host file path). */
+pf_status pf_tune_load(const char *path);
+pf_status pf_tune_save(const char *path);
+/* Measure every candidate for kinds {2D, SEP}, r in 0..r_max and the three
+ * size classes on the current device with hipEvents (median of `reps`
+ * timed runs over rotated buffers), install the winners, and write the
+ * table to `path` if it is not NULL. Allocates and frees its own device
+ * buffers; synchronises the device. */
+pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path);
+
+/* ---- batch: many images, one persistent launch ---------------------------
+ * n images described by host arrays (sizes first): image i has h[i] x w[i]
+ * pixels at in + pix_off[i] and out + pix_off[i], radius r[i], filter kind
+ * kind[i] with weights at filt + filt_off[i]. Offsets are in elements.
+ * Plan creation validates everything (ranges inside npix / nfilt, images
+ * disjoint), chooses each image's variant and shape from the tune table,
+ * builds the tile table and uploads it to the device. The plan owns that
+ * device table (and, with PF_BATCH_GRAPH, a captured hipGraph).
+ * Variant choice depends only on (kind, r, pixels), never on the rest of
+ * the batch, so each image's result equals what the single-image call with
+ * the same variant computes, bit for bit. */
+typedef struct pf_batch_plan pf_batch_plan;
+
+pf_status pf_batch_plan_create(int32_t n,
+                               PF_ARR(const int32_t, h, n), PF_ARR(const int32_t, w, n),
+                               PF_ARR(const int32_t, r, n), PF_ARR(const int32_t, kind, n),
+                               PF_ARR(const int64_t, pix_off, n), PF_ARR(const int64_t, filt_off, n),
+                               int64_t npix, int64_t nfilt, int32_t flags,
+                               PF_OUTP(pf_batch_plan *, plan));
+/* Run the plan: in, out: float[npix] device arenas (disjoint); filt:
+ * float[nfilt] device arena. npix and nfilt must equal the plan's. With
+ * PF_BATCH_GRAPH the launch is a graph replay; new arena pointers are
+ * patched into the graph's kernel nodes before the replay. */
+pf_status pf_batch_plan_run(pf_batch_plan *plan, int64_t npix, int64_t nfilt,
+                            PF_ARR(const float, in, npix), PF_ARR(const float, filt, nfilt),
+                            PF_ARR(float, out, npix), void *stream);
+/* Per-image variant chosen by the plan (host array of n entries). */
+pf_status pf_batch_plan_variants(const pf_batch_plan *plan, int32_t n, PF_ARR(int32_t, variant, n));
+/* tasks: wave tiles in the plan; launches: kernels per run (1 or 2);
+ * grid: workgroups of the main persistent launch. */
+pf_status pf_batch_plan_info(const pf_batch_plan *plan, PF_OUTP(int64_t, tasks),
+                             PF_OUTP(int32_t, launches), PF_OUTP(int32_t, grid));
+pf_status pf_batch_plan_destroy(pf_batch_plan *plan);
+
+/* ---- serving: continuous batching under an HBM budget ----------------------
+ * A server owns a device arena of `hbm_budget_bytes` (outputs, uploaded
+ * inputs, weights), `n_streams` HIP streams and an engine thread. Requests
+ * are admitted first-come first-served while their bytes fit in the
+ * budget; admitted requests are packed into batches of at most
+ * `max_batch` images and launched on whichever stream is free, so new
+ * arrivals run while earlier batches are still on the device.
+ * A request's result does not depend on which batch it lands in. */
+typedef struct pf_server pf_server;
+
+typedef struct pf_server_stats {
+    int64_t submitted, admitted, completed, rejected;
+    int64_t batches;              /* batches launched                          */
+    int64_t pixels;               /* output pixels completed                   */
+    int64_t bytes_high_water;     /* largest arena reservation seen            */
+    int64_t queue_high_water;     /* largest number of waiting requests        */
+    double  mean_batch;           /* requests per batch                        */
+    double  p50_us, p99_us, p999_us, max_us;   /* completion - arrival         */
+    double  wall_s;               /* first arrival to last completion          */
+    double  gpx_per_s;            /* pixels / wall_s / 1e9                     */
+} pf_server_stats;
+
+/* n_streams 1..8, max_batch 1..4096, max_queue >= 1 (waiting requests). */
+pf_status pf_server_create(int64_t hbm_budget_bytes, int32_t n_streams, int32_t max_batch,
+                           int32_t max_queue, int32_t flags, PF_OUTP(pf_server *, srv));
+/* Submit one request (sizes first). `in` is float[h*w]: a device pointer
+ * that stays resident and unmodified until the request completes, or, if
+ * in_is_host != 0, a host pointer copied into the arena before submit
+ * returns. `filt` is a HOST array of the kind's weights, copied. The
+ * arrival time (ns on CLOCK_MONOTONIC; 0 = now) is the origin of the
+ * request's latency. PF_EBUDGET if the request alone exceeds the budget,
+ * PF_EAGAIN if max_queue requests are already waiting. */
+pf_status pf_server_submit(pf_server *s, int32_t h, int32_t w, int32_t r, int32_t kind,
+                           const float *in, int32_t in_is_host,
+                           const float *filt, int64_t arrival_ns,
+                           PF_OUTP(int64_t, ticket));
+/* done = 1 once the request's output is complete on the device. */
+pf_status pf_server_poll(pf_server *s, int64_t ticket, PF_OUTP(int32_t, done));
+/* Block until done or timeout (ns; < 0 waits forever): PF_ETIMEDOUT. */
+pf_status pf_server_wait(pf_server *s, int64_t ticket, int64_t timeout_ns);
+/* Copy the finished output (float[h*w]) to `out` (host if out_is_host,
+ * else device) and release the request's arena bytes and ticket. */
+pf_status pf_server_result(pf_server *s, int64_t ticket, int32_t h, int32_t w,
+                           float *out, int32_t out_is_host);
+/* Release a finished request without copying its output. */
+pf_status pf_server_release(pf_server *s, int64_t ticket);
+pf_status pf_server_stats_get(pf_server *s, PF_OUTP(pf_server_stats, st));
+/* Open-loop load generator: submit n requests at their scheduled times
+ * (arrival_ns[i], relative to the call's start), request i filtering
+ * h[i] x w[i] pixels at in + pix_off[i] (device arena of npix floats) with
+ * radius r[i] and host weights filt + filt_off[i] (kind PF_KIND_SEP), and
+ * release each output as it completes. Returns when all have completed;
+ * latencies are recorded in the server's stats. */
+pf_status pf_server_run_trace(pf_server *s, int32_t n,
+                              PF_ARR(const int64_t, arrival_ns, n),
+                              PF_ARR(const int32_t, h, n), PF_ARR(const int32_t, w, n),
+                              PF_ARR(const int32_t, r, n),
+                              PF_ARR(const int64_t, pix_off, n), PF_ARR(const int64_t, filt_off, n),
+                              int64_t npix, const float *in, int64_t nfilt, const float *filt);
+/* Drain in-flight work, then free everything the server owns. */
+pf_status pf_server_destroy(pf_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PENCILFILTER_PF_H */

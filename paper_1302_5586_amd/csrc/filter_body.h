@@ -1,0 +1,598 @@
+// HIP kernels for gfx950 (MI355X): clamp-to-edge 2D image filters.
+//
+// The filter is a stencil, the "regular algorithm" class the paper names
+// (Sec. II), over an affine loop nest whose output iterations are
+// independent (Sec. II-B.3), so every output element may be computed by any
+// lane in any order. The paper's own code generation targets OpenCL through
+// polyhedral tiling; these kernels are written directly for CDNA4 instead:
+//
+//  * A wave owns a strip of 64 lanes x 4 columns. The outermost lanes on
+//    each side only load halo columns; the inner lanes each produce 4
+//    output columns. Horizontal neighbours come from the adjacent lanes
+//    through DPP wavefront shifts (v_mov_b32_dpp wave_shr/wave_shl), so
+//    the halo never passes through LDS or a second global load.
+//  * The wave walks down its strip one input row at a time (one 16-byte
+//    load per lane per row). Each input row is folded into the 2r+1
+//    output rows it touches, held in a ring of register accumulators, so
+//    every input element is read from memory once per strip and vertical
+//    halo rows are re-read only at strip ends.
+//  * Taps are accumulated per output in the definition's order (dy outer,
+//    dx inner, ascending). By default each tap is one fused multiply-add;
+//    the EXACT instantiation uses a separate multiply and add (this file is
+//    built with -ffp-contract=off) and reproduces the sequential C program
+//    bit for bit.
+//  * The separable variant does the row pass on the DPP window and the
+//    column pass on the register ring: the FP32 intermediate never leaves
+//    registers (8 bytes of HBM traffic per pixel instead of 16).
+//  * The uint8 path packs 4 taps per v_dot4c_i32_i8. Pixels are biased by
+//    -128 (xor 0x80) to fit the signed operand and the bias is added back
+//    exactly as 128 * sum(weights).
+//  * No LDS and no barriers: waves of a workgroup are independent, so
+//    every wave exits on its own.
+//
+// Workgroup ids are remapped so that consecutive tiles land on the same
+// XCD (workgroups are dealt round-robin over the 8 XCDs), which keeps the
+// rows shared by vertically adjacent strips in one L2.
+#pragma once
+
+#include <type_traits>
+
+#include "pf_internal.h"
+
+namespace pf {
+namespace dev {
+
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+
+constexpr int kLanes = 64;
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// DPP wavefront shifts: lane i receives lane i-1 (from_left) or lane i+1
+// (from_right). Lanes with no source lane receive 0; they are halo lanes
+// whose outputs are never stored.
+__device__ __forceinline__ float from_left(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_right(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ int from_left_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int from_right_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give the
+// workgroups that share an XCD consecutive logical ids.
+__device__ __forceinline__ int xcd_remap(int b, int g) {
+    const int xcd = b & 7, idx = b >> 3;
+    const int per = g >> 3, rem = g & 7;
+    return xcd * per + min(xcd, rem) + idx;
+}
+
+template <bool EXACT>
+__device__ __forceinline__ float madd(float wgt, float x, float acc) {
+    if constexpr (EXACT) {
+        const float p = wgt * x;  // no contraction: -ffp-contract=off
+        return acc + p;
+    } else {
+        return __builtin_fmaf(wgt, x, acc);
+    }
+}
+
+// Four consecutive elements of a row from column xs, clamped to [0, w-1].
+// The fast path is one dwordx4 load; rows need only 4-byte alignment.
+__device__ __forceinline__ void load4(const float *__restrict__ row, int xs, int w, float v[4]) {
+    if (xs >= 0 && xs + 3 < w) {
+        const f4u q = *reinterpret_cast<const f4u *>(row + xs);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = row[clampi(xs + k, 0, w - 1)];
+    }
+}
+
+__device__ __forceinline__ void store4(float *__restrict__ row, int xs, int w, const float v[4]) {
+    if (xs + 3 < w) {
+        f4u q;
+        q.x = v[0];
+        q.y = v[1];
+        q.z = v[2];
+        q.w = v[3];
+        *reinterpret_cast<f4u *>(row + xs) = q;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (xs + k < w) row[xs + k] = v[k];
+    }
+}
+
+// ---------------------------------------------------------------- FP32 ---
+
+template <int R, int VAR>
+struct Weights {
+    static constexpr int K = 2 * R + 1;
+    static constexpr bool SEP = (VAR == PF_VAR_SEPARABLE);
+    float w2[SEP ? 1 : K * K];
+    float fx[SEP ? K : 1];
+    float fy[SEP ? K : 1];
+
+    // fa: the (2R+1)^2 taps (DIRECT) or fx (separable kinds); fb: fy.
+    __device__ __forceinline__ Weights(const float *__restrict__ fa, const float *__restrict__ fb) {
+        if constexpr (VAR == PF_VAR_DIRECT) {
+#pragma unroll
+            for (int i = 0; i < K * K; ++i) w2[i] = fa[i];
+        } else if constexpr (VAR == PF_VAR_SEPARABLE) {
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                fx[i] = fa[i];
+                fy[i] = fb[i];
+            }
+        } else {
+            // 2D taps of a separable filter: fy[a] * fx[b] rounded once to FP32.
+#pragma unroll
+            for (int a = 0; a < K; ++a)
+#pragma unroll
+                for (int b = 0; b < K; ++b) w2[a * K + b] = fb[a] * fa[b];
+        }
+    }
+};
+
+// Fold one input row into the accumulator ring.
+//   RES: the row's index modulo K (compile time).
+//   IPRO >= 0: the row is prologue row IPRO (< 2R): skip outputs j < 0.
+// Output j of the strip collects input rows j .. j+2R (dy = -R .. R) and
+// lives in ring slot j mod K.
+template <int R, int VAR, bool EXACT, int RES, int IPRO>
+__device__ __forceinline__ void fold_row_f32(const Weights<R, VAR> &wt, const float v[4],
+                                             float (&acc)[2 * R + 1][4]) {
+    constexpr int K = 2 * R + 1;
+    constexpr int NB = halo_lanes(R);
+    constexpr int C = 4 * NB;
+    constexpr int NW = 4 * (2 * NB + 1);
+    float win[NW];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) win[C + k] = v[k];
+    {
+        float l[4] = {v[0], v[1], v[2], v[3]};
+        float r[4] = {v[0], v[1], v[2], v[3]};
+#pragma unroll
+        for (int m = 1; m <= NB; ++m) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                l[k] = from_left(l[k]);
+                r[k] = from_right(r[k]);
+                win[C - 4 * m + k] = l[k];
+                win[C + 4 * m + k] = r[k];
+            }
+        }
+    }
+    if constexpr (VAR == PF_VAR_SEPARABLE) {
+        float t[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            t[k] = 0.0f;
+#pragma unroll
+            for (int dx = -R; dx <= R; ++dx) t[k] = madd<EXACT>(wt.fx[dx + R], win[C + k + dx], t[k]);
+        }
+#pragma unroll
+        for (int dy = -R; dy <= R; ++dy) {
+            // output j = i - R - dy; in the prologue i = IPRO and j < 0 is skipped
+            if (IPRO >= 0 && IPRO - R - dy < 0) continue;
+            const int slot = ((RES - R - dy) % K + K) % K;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[slot][k] = madd<EXACT>(wt.fy[dy + R], t[k], acc[slot][k]);
+        }
+    } else {
+#pragma unroll
+        for (int dy = -R; dy <= R; ++dy) {
+            if (IPRO >= 0 && IPRO - R - dy < 0) continue;
+            const int slot = ((RES - R - dy) % K + K) % K;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int dx = -R; dx <= R; ++dx)
+                    acc[slot][k] = madd<EXACT>(wt.w2[(dy + R) * K + dx + R], win[C + k + dx], acc[slot][k]);
+        }
+    }
+}
+
+// Input rows [i0, i0 + K) of a strip, all present; i0 = 2R + q*K so row
+// i0 + s has ring residue (2R + s) mod K.
+template <int R, int VAR, bool EXACT>
+__device__ __forceinline__ void chunk_f32(const Weights<R, VAR> &wt, const float *__restrict__ in,
+                                          float *__restrict__ out, float (&acc)[2 * R + 1][4], int h,
+                                          int w, int xs, int y0, int rows, int i0, bool out_lane) {
+    constexpr int K = 2 * R + 1;
+    float v[K][4];
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const int yy = clampi(y0 - R + i0 + s, 0, h - 1);
+        load4(in + (int64_t)yy * w, xs, w, v[s]);
+    }
+    static_for<0, K>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        constexpr int RES = (2 * R + s) % K;
+        fold_row_f32<R, VAR, EXACT, RES, -1>(wt, v[s], acc);
+        const int j = i0 + s - 2 * R;  // output completed by this row
+        constexpr int done = (RES + 1) % K;
+        if (j < rows && out_lane) store4(out + (int64_t)(y0 + j) * w, xs, w, acc[done]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[done][k] = 0.0f;
+    });
+}
+
+// Up to K input rows from i0 (each only if present); i0 = OFF (mod K).
+// Used for the rows left after the last full chunk, and as the whole row
+// loop of the compact form for large radii.
+template <int R, int VAR, bool EXACT, int OFF>
+__device__ __forceinline__ void tail_f32(const Weights<R, VAR> &wt, const float *__restrict__ in,
+                                         float *__restrict__ out, float (&acc)[2 * R + 1][4], int h, int w,
+                                         int xs, int y0, int rows, int i0, int nin, bool out_lane) {
+    constexpr int K = 2 * R + 1;
+    static_for<0, K>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        if (i0 + s < nin) {
+            constexpr int RES = (OFF + s) % K;
+            float v[4];
+            const int yy = clampi(y0 - R + i0 + s, 0, h - 1);
+            load4(in + (int64_t)yy * w, xs, w, v);
+            fold_row_f32<R, VAR, EXACT, RES, -1>(wt, v, acc);
+            const int j = i0 + s - 2 * R;
+            constexpr int done = (RES + 1) % K;
+            if (j >= 0 && j < rows && out_lane) store4(out + (int64_t)(y0 + j) * w, xs, w, acc[done]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[done][k] = 0.0f;
+        }
+    });
+}
+
+// One wave computes output rows [y0, y0 + rows) of columns [x0, x0 + strip
+// width) of one image plane.
+template <int R, int VAR, bool EXACT>
+__device__ __forceinline__ void strip_f32(const float *__restrict__ in, const float *__restrict__ fa,
+                                          const float *__restrict__ fb, float *__restrict__ out, int h, int w,
+                                          int x0, int y0, int rows, int lane) {
+    constexpr int K = 2 * R + 1;
+    constexpr int NB = halo_lanes(R);
+    const Weights<R, VAR> wt(fa, fb);
+    const int xs = x0 + 4 * (lane - NB);
+    const bool out_lane = (lane >= NB) && (lane < kLanes - NB) && (xs < w);
+    float acc[K][4];
+#pragma unroll
+    for (int s = 0; s < K; ++s)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[s][k] = 0.0f;
+
+    const int nin = rows + 2 * R;
+    if constexpr (R > 4) {
+        // Compact form for large radii: one guarded copy of the K-row body
+        // (the first 2R rows fold into outputs j < 0 that are never stored).
+        for (int i0 = 0; i0 < nin; i0 += K) tail_f32<R, VAR, EXACT, 0>(wt, in, out, acc, h, w, xs, y0, rows, i0, nin, out_lane);
+    } else {
+        if constexpr (R > 0) {
+            // Prologue: input rows 0 .. 2R-1 complete no output.
+            float v[2 * R][4];
+#pragma unroll
+            for (int i = 0; i < 2 * R; ++i) {
+                const int yy = clampi(y0 - R + i, 0, h - 1);
+                load4(in + (int64_t)yy * w, xs, w, v[i]);
+            }
+            static_for<0, 2 * R>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                fold_row_f32<R, VAR, EXACT, i % K, i>(wt, v[i], acc);
+            });
+        }
+        int i0 = 2 * R;
+        for (; i0 + K <= nin; i0 += K) chunk_f32<R, VAR, EXACT>(wt, in, out, acc, h, w, xs, y0, rows, i0, out_lane);
+        tail_f32<R, VAR, EXACT, (2 * R) % K>(wt, in, out, acc, h, w, xs, y0, rows, i0, nin, out_lane);
+    }
+}
+
+// Single-image kernel: one wave tile per task, tasks column-major over
+// (strip x, strip y) so the waves of a workgroup are vertically adjacent.
+template <int R, int VAR, bool EXACT>
+__global__ __launch_bounds__(512) void k_filter_f32(const float *__restrict__ in, const float *__restrict__ fa,
+                                                    const float *__restrict__ fb, float *__restrict__ out, int h,
+                                                    int w, int by,
+                                                    int strips_y, int ntasks) {
+    const int wpg = blockDim.x / kLanes;
+    const int wave = uniform(threadIdx.x / kLanes);
+    const int lane = threadIdx.x % kLanes;
+    const int t = xcd_remap(blockIdx.x, gridDim.x) * wpg + wave;
+    if (t >= ntasks) return;
+    const int sx = t / strips_y, sy = t - sx * strips_y;
+    const int y0 = sy * by;
+    strip_f32<R, VAR, EXACT>(in, fa, fb, out, h, w, sx * strip_width(R), y0, min(by, h - y0), lane);
+}
+
+// Persistent batch kernel: a fixed grid of workgroups walks the flattened
+// wave-tile list of all images with a static stride. task_img[t] names the
+// image of task t; the image descriptor gives its radius, variant, tile
+// height and arena offsets.
+template <int RLO, int RHI, bool EXACT, int VMASK>
+__global__ __launch_bounds__(512) void k_batch_f32(const BatchImg *__restrict__ imgs,
+                                                   const int32_t *__restrict__ task_img, int ntasks,
+                                                   const float *__restrict__ in, const float *__restrict__ filt,
+                                                   float *__restrict__ out) {
+    const int wpg = blockDim.x / kLanes;
+    const int wave = uniform(threadIdx.x / kLanes);
+    const int lane = threadIdx.x % kLanes;
+    const int stride = gridDim.x * wpg;
+    for (int t = xcd_remap(blockIdx.x, gridDim.x) * wpg + wave; t < ntasks; t += stride) {
+        const int i = uniform(task_img[t]);
+        const BatchImg d = imgs[i];
+        const int local = t - d.task_base;
+        const int sx = local / d.strips_y, sy = local - sx * d.strips_y;
+        const int y0 = sy * d.by;
+        const int rows = min(d.by, d.h - y0);
+        const float *src = reinterpret_cast<const float *>(reinterpret_cast<uintptr_t>(in) + (uint64_t)d.in_off * 4u);
+        float *dst = reinterpret_cast<float *>(reinterpret_cast<uintptr_t>(out) + (uint64_t)d.out_off * 4u);
+        const float *fa = reinterpret_cast<const float *>(reinterpret_cast<uintptr_t>(filt) + (uint64_t)d.filt_off * 4u);
+        const float *fb = fa + 2 * d.r + 1;
+        // Only the variants in VMASK are compiled in: the register budget of
+        // the kernel is the largest of its bodies.
+        static_for<RLO, RHI + 1>([&](auto rc) {
+            constexpr int RR = decltype(rc)::value;
+            if (d.r == RR) {
+                static_for<0, 3>([&](auto vc) {
+                    constexpr int VV = decltype(vc)::value;
+                    if constexpr ((VMASK >> VV) & 1) {
+                        if (d.var == VV)
+                            strip_f32<RR, VV, EXACT>(src, fa, fb, dst, d.h, d.w, sx * strip_width(RR), y0, rows, lane);
+                    }
+                });
+            }
+        });
+    }
+}
+
+// --------------------------------------------------------------- uint8 ---
+
+constexpr int floordiv4(int u) { return u >= 0 ? u / 4 : -((-u + 3) / 4); }
+
+template <int R>
+struct WeightsU8 {
+    static constexpr int K = 2 * R + 1;
+    static constexpr int ND = (K + 3) / 4;  // dwords per filter row
+    static constexpr int PAD = 4 * ND - K;  // zero taps in front of each row
+    int32_t wd[K][ND];
+    int32_t bias;  // 128 * sum of weights
+
+    __device__ __forceinline__ explicit WeightsU8(const int8_t *__restrict__ filt) {
+        int s = 0;
+#pragma unroll
+        for (int dy = 0; dy < K; ++dy) {
+#pragma unroll
+            for (int m = 0; m < ND; ++m) {
+                uint32_t pk = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int t = 4 * m + b - PAD;
+                    if (t >= 0 && t < K) {
+                        const int8_t q = filt[dy * K + t];
+                        s += q;
+                        pk |= (uint32_t)(uint8_t)q << (8 * b);
+                    }
+                }
+                wd[dy][m] = (int32_t)pk;
+            }
+        }
+        bias = 128 * s;
+    }
+};
+
+__device__ __forceinline__ uint32_t load4_u8(const uint8_t *__restrict__ row, int xs, int w, bool aligned) {
+    if (aligned && xs >= 0 && xs + 3 < w) return *reinterpret_cast<const uint32_t *>(row + xs);
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v |= (uint32_t)row[clampi(xs + k, 0, w - 1)] << (8 * k);
+    return v;
+}
+
+template <int R, int RES, int IPRO>
+__device__ __forceinline__ void fold_row_u8(const WeightsU8<R> &wt, uint32_t own, int (&acc)[2 * R + 1][4]) {
+    constexpr int K = 2 * R + 1;
+    constexpr int NB = halo_lanes(R);
+    constexpr int ND = WeightsU8<R>::ND;
+    constexpr int PAD = WeightsU8<R>::PAD;
+    uint32_t win[2 * NB + 1];
+    win[NB] = own ^ 0x80808080u;  // p - 128 as signed bytes
+    {
+        int l = (int)win[NB], r = (int)win[NB];
+#pragma unroll
+        for (int m = 1; m <= NB; ++m) {
+            l = from_left_i(l);
+            r = from_right_i(r);
+            win[NB - m] = (uint32_t)l;
+            win[NB + m] = (uint32_t)r;
+        }
+    }
+    // D[k][m]: the 4 bytes multiplied by filter dword m for output column k.
+    int32_t D[4][ND];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int m = 0; m < ND; ++m) {
+            const int u0 = k - R - PAD + 4 * m + 4 * NB;  // window byte of the dword's first byte
+            const int lo = floordiv4(u0);
+            const int sh = u0 - 4 * lo;
+            const uint32_t a = (lo >= 0 && lo <= 2 * NB) ? win[lo >= 0 && lo <= 2 * NB ? lo : 0] : 0u;
+            const uint32_t b = (lo + 1 >= 0 && lo + 1 <= 2 * NB) ? win[lo + 1 >= 0 && lo + 1 <= 2 * NB ? lo + 1 : 0] : 0u;
+            D[k][m] = (int32_t)(sh == 0 ? a : __builtin_amdgcn_alignbyte(b, a, sh));
+        }
+    }
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy) {
+        if (IPRO >= 0 && IPRO - R - dy < 0) continue;
+        const int slot = ((RES - R - dy) % K + K) % K;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int m = 0; m < ND; ++m) acc[slot][k] = __builtin_amdgcn_sdot4(D[k][m], wt.wd[dy + R][m], acc[slot][k], false);
+    }
+}
+
+__device__ __forceinline__ void store4_u8(uint8_t *__restrict__ row, int xs, int w, bool aligned,
+                                          const int (&a)[4], int bias, int shift) {
+    uint32_t pk = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int q = (a[k] + bias) >> shift;  // arithmetic shift of a signed int
+        pk |= (uint32_t)clampi(q, 0, 255) << (8 * k);
+    }
+    if (aligned && xs + 3 < w) {
+        *reinterpret_cast<uint32_t *>(row + xs) = pk;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (xs + k < w) row[xs + k] = (uint8_t)(pk >> (8 * k));
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void strip_u8(const uint8_t *__restrict__ in, const int8_t *__restrict__ filt,
+                                         uint8_t *__restrict__ out, int h, int w, int shift, bool aligned,
+                                         int x0, int y0, int rows, int lane) {
+    constexpr int K = 2 * R + 1;
+    constexpr int NB = halo_lanes(R);
+    const WeightsU8<R> wt(filt);
+    const int xs = x0 + 4 * (lane - NB);
+    const bool out_lane = (lane >= NB) && (lane < kLanes - NB) && (xs < w);
+    int acc[K][4];
+#pragma unroll
+    for (int s = 0; s < K; ++s)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[s][k] = 0;
+    if constexpr (R > 0) {
+        uint32_t v[2 * R];
+#pragma unroll
+        for (int i = 0; i < 2 * R; ++i) v[i] = load4_u8(in + (int64_t)clampi(y0 - R + i, 0, h - 1) * w, xs, w, aligned);
+        static_for<0, 2 * R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            fold_row_u8<R, i % K, i>(wt, v[i], acc);
+        });
+    }
+    const int nin = rows + 2 * R;
+    int i0 = 2 * R;
+    for (; i0 + K <= nin; i0 += K) {
+        uint32_t v[K];
+#pragma unroll
+        for (int s = 0; s < K; ++s) v[s] = load4_u8(in + (int64_t)clampi(y0 - R + i0 + s, 0, h - 1) * w, xs, w, aligned);
+        static_for<0, K>([&](auto sc) {
+            constexpr int s = decltype(sc)::value;
+            constexpr int RES = (2 * R + s) % K;
+            fold_row_u8<R, RES, -1>(wt, v[s], acc);
+            const int j = i0 + s - 2 * R;
+            constexpr int done = (RES + 1) % K;
+            if (j < rows && out_lane) store4_u8(out + (int64_t)(y0 + j) * w, xs, w, aligned, acc[done], wt.bias, shift);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[done][k] = 0;
+        });
+    }
+    static_for<0, K>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        if (i0 + s < nin) {
+            constexpr int RES = (2 * R + s) % K;
+            const uint32_t v = load4_u8(in + (int64_t)clampi(y0 - R + i0 + s, 0, h - 1) * w, xs, w, aligned);
+            fold_row_u8<R, RES, -1>(wt, v, acc);
+            const int j = i0 + s - 2 * R;
+            constexpr int done = (RES + 1) % K;
+            if (j < rows && out_lane) store4_u8(out + (int64_t)(y0 + j) * w, xs, w, aligned, acc[done], wt.bias, shift);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[done][k] = 0;
+        }
+    });
+}
+
+template <int R>
+__global__ __launch_bounds__(512) void k_filter_u8(const uint8_t *__restrict__ in, const int8_t *__restrict__ filt,
+                                                   uint8_t *__restrict__ out, int h, int w, int shift, int aligned,
+                                                   int by, int strips_y, int tasks_per_plane, int ntasks) {
+    const int wpg = blockDim.x / kLanes;
+    const int wave = uniform(threadIdx.x / kLanes);
+    const int lane = threadIdx.x % kLanes;
+    const int t = xcd_remap(blockIdx.x, gridDim.x) * wpg + wave;
+    if (t >= ntasks) return;
+    const int p = t / tasks_per_plane;
+    const int local = t - p * tasks_per_plane;
+    const int sx = local / strips_y, sy = local - sx * strips_y;
+    const int y0 = sy * by;
+    const int64_t plane = (int64_t)p * h * w;
+    strip_u8<R>(in + plane, filt, out + plane, h, w, shift, aligned != 0, sx * strip_width(R), y0,
+                min(by, h - y0), lane);
+}
+
+}  // namespace dev
+}  // namespace pf
+
+
+// ------------------------------------------------------------ launchers ---
+namespace pf {
+namespace dev {
+
+inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+template <int R, int VAR, bool EXACT>
+hipError_t launch_f32_t(const float *in, const float *fa, const float *fb, float *out, int h, int w, int by, int wpg,
+                        hipStream_t s) {
+    const int sw = strip_width(R);
+    const int strips_x = cdiv(w, sw), strips_y = cdiv(h, by);
+    const int64_t ntasks64 = (int64_t)strips_x * strips_y;
+    if (ntasks64 > INT32_MAX) return hipErrorInvalidValue;
+    const int ntasks = (int)ntasks64;
+    const int grid = cdiv(ntasks, wpg);
+    hipLaunchKernelGGL((k_filter_f32<R, VAR, EXACT>), dim3(grid), dim3(wpg * kLanes), 0, s, in, fa, fb, out, h, w,
+                       by, strips_y, ntasks);
+    return hipGetLastError();
+}
+
+template <int R, bool EXACT>
+hipError_t launch_f32_v(int var, const float *in, const float *fa, const float *fb, float *out, int h, int w, int by,
+                        int wpg, hipStream_t s) {
+    switch (var) {
+        case PF_VAR_DIRECT:
+            return launch_f32_t<R, PF_VAR_DIRECT, EXACT>(in, fa, fb, out, h, w, by, wpg, s);
+        case PF_VAR_SEPARABLE:
+            return launch_f32_t<R, PF_VAR_SEPARABLE, EXACT>(in, fa, fb, out, h, w, by, wpg, s);
+        case PF_VAR_SEP_DIRECT:
+            return launch_f32_t<R, PF_VAR_SEP_DIRECT, EXACT>(in, fa, fb, out, h, w, by, wpg, s);
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+template <int R>
+hipError_t launch_u8_t(const uint8_t *in, const int8_t *filt, uint8_t *out, int c, int h, int w, int shift, int by,
+                       int wpg, hipStream_t s) {
+    const int sw = strip_width(R);
+    const int strips_x = cdiv(w, sw), strips_y = cdiv(h, by);
+    const int64_t per_plane = (int64_t)strips_x * strips_y;
+    const int64_t ntasks64 = per_plane * c;
+    if (ntasks64 > INT32_MAX) return hipErrorInvalidValue;
+    const int ntasks = (int)ntasks64;
+    const int grid = cdiv(ntasks, wpg);
+    const int aligned = (w % 4 == 0) && ((uintptr_t)in % 4 == 0) && ((uintptr_t)out % 4 == 0);
+    hipLaunchKernelGGL((k_filter_u8<R>), dim3(grid), dim3(wpg * kLanes), 0, s, in, filt, out, h, w, shift, aligned,
+                       by, strips_y, (int)per_plane, ntasks);
+    return hipGetLastError();
+}
+
+}  // namespace dev
+}  // namespace pf

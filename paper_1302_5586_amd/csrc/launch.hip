@@ -1,0 +1,69 @@
+// Radius dispatch for the single-image kernels, the uint8 kernels and the
+// batch kernels' entry points.
+#include "filter_body.h"
+
+namespace pf {
+
+hipError_t launch_f32(int r, int var, bool exact, const float *in, const float *fa, const float *fb, float *out,
+                      int h, int w, int by, int wpg, hipStream_t s) {
+    switch (r) {
+        case 0: return launch_f32_radius<0>(var, exact, in, fa, fb, out, h, w, by, wpg, s);
+        case 1: return launch_f32_radius<1>(var, exact, in, fa, fb, out, h, w, by, wpg, s);
+        case 2: return launch_f32_radius<2>(var, exact, in, fa, fb, out, h, w, by, wpg, s);
+        case 3: return launch_f32_radius<3>(var, exact, in, fa, fb, out, h, w, by, wpg, s);
+        case 4: return launch_f32_radius<4>(var, exact, in, fa, fb, out, h, w, by, wpg, s);
+        case 5: return launch_f32_radius<5>(var, exact, in, fa, fb, out, h, w, by, wpg, s);
+        case 6: return launch_f32_radius<6>(var, exact, in, fa, fb, out, h, w, by, wpg, s);
+        case 7: return launch_f32_radius<7>(var, exact, in, fa, fb, out, h, w, by, wpg, s);
+        case 8: return launch_f32_radius<8>(var, exact, in, fa, fb, out, h, w, by, wpg, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_u8(int r, const uint8_t *in, const int8_t *filt, uint8_t *out, int c, int h, int w, int shift,
+                     int by, int wpg, hipStream_t s) {
+    switch (r) {
+        case 0: return dev::launch_u8_t<0>(in, filt, out, c, h, w, shift, by, wpg, s);
+        case 1: return dev::launch_u8_t<1>(in, filt, out, c, h, w, shift, by, wpg, s);
+        case 2: return dev::launch_u8_t<2>(in, filt, out, c, h, w, shift, by, wpg, s);
+        case 3: return dev::launch_u8_t<3>(in, filt, out, c, h, w, shift, by, wpg, s);
+        case 4: return dev::launch_u8_t<4>(in, filt, out, c, h, w, shift, by, wpg, s);
+        case 5: return dev::launch_u8_t<5>(in, filt, out, c, h, w, shift, by, wpg, s);
+        case 6: return dev::launch_u8_t<6>(in, filt, out, c, h, w, shift, by, wpg, s);
+        case 7: return dev::launch_u8_t<7>(in, filt, out, c, h, w, shift, by, wpg, s);
+        case 8: return dev::launch_u8_t<8>(in, filt, out, c, h, w, shift, by, wpg, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+void *batch_kernel_fn(int group, bool exact, int mask) {
+    if (group == 1) return exact ? batch_fn<1, 1, 3>() : batch_fn<1, 0, 3>();
+    switch (mask) {
+        case 2: return exact ? batch_fn<0, 1, 2>() : batch_fn<0, 0, 2>();
+        case 3: return exact ? batch_fn<0, 1, 3>() : batch_fn<0, 0, 3>();
+        default: return exact ? batch_fn<0, 1, 7>() : batch_fn<0, 0, 7>();
+    }
+}
+
+int batch_grid_limit(int group, bool exact, int mask, int wpg) {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel_fn(group, exact, mask), wpg * dev::kLanes,
+                                                     0) != hipSuccess ||
+        blocks < 1)
+        blocks = 1;
+    return blocks * dev_info().cus;
+}
+
+hipError_t launch_batch(int group, bool exact, int mask, const BatchImg *imgs, const int32_t *task_img, int ntasks,
+                        int grid, int wpg, const float *in, const float *filt, float *out, hipStream_t s) {
+#define PF_LB(G, E, M) launch_batch_g<G, E, M>(imgs, task_img, ntasks, grid, wpg, in, filt, out, s)
+    if (group == 1) return exact ? PF_LB(1, 1, 3) : PF_LB(1, 0, 3);
+    switch (mask) {
+        case 2: return exact ? PF_LB(0, 1, 2) : PF_LB(0, 0, 2);
+        case 3: return exact ? PF_LB(0, 1, 3) : PF_LB(0, 0, 3);
+        default: return exact ? PF_LB(0, 1, 7) : PF_LB(0, 0, 7);
+    }
+#undef PF_LB
+}
+
+}  // namespace pf

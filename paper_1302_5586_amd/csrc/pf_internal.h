@@ -1,0 +1,123 @@
+// Internal declarations shared by the library's translation units.
+// Nothing here is part of the C ABI (that is include/pf.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "pf.h"
+
+namespace pf {
+
+// Output columns one wave covers: 64 lanes of 4 columns, minus the halo
+// lanes on each side (one per 4 columns of radius).
+constexpr int halo_lanes(int r) { return (r + 3) / 4; }
+constexpr int strip_width(int r) { return 4 * (64 - 2 * halo_lanes(r)); }
+
+// One image of a batch as the persistent kernel sees it. `var` is the
+// executed variant (PF_VAR_*), `by` rows per wave tile, tasks are numbered
+// column-major over (strip x, strip y) inside the image.
+// Element offsets are added to the kernel's base pointers as integers, so a
+// descriptor may also carry an absolute address (byte address / 4) with a
+// null base.
+struct BatchImg {
+    int64_t in_off;
+    int64_t out_off;
+    int64_t filt_off;
+    int32_t h, w, r, var;
+    int32_t by, strips_y, task_base, pad;
+};
+
+// Size class used by the tune table.
+inline int size_class(int64_t pixels) {
+    return pixels < 256 * 256 ? 0 : (pixels > 1024 * 1024 ? 2 : 1);
+}
+
+// Device properties the launchers need (cached per device).
+struct DevInfo {
+    int device = -1;
+    int cus = 0;
+    std::string arch;
+};
+const DevInfo &dev_info();
+
+// Thread-local error text.
+pf_status fail(pf_status s, const std::string &msg);
+pf_status fail_hip(hipError_t e, const char *what);
+void clear_error();
+
+// Launchers (kernels.hip). All validate nothing: callers have already.
+// fa: 2D taps (PF_VAR_DIRECT) or fx; fb: fy (ignored for PF_VAR_DIRECT).
+hipError_t launch_f32(int r, int var, bool exact, const float *in, const float *fa, const float *fb, float *out,
+                      int h, int w, int by, int wpg, hipStream_t s);
+hipError_t launch_u8(int r, const uint8_t *in, const int8_t *filt, uint8_t *out, int c, int h,
+                     int w, int shift, int by, int wpg, hipStream_t s);
+// Persistent batch kernel over images with r <= 4 (group 0) or r in 5..8
+// (group 1), compiled with the variants of `mask` (see batch_mask).
+hipError_t launch_batch(int group, bool exact, int mask, const BatchImg *imgs, const int32_t *task_img,
+                        int ntasks, int grid, int wpg, const float *in, const float *filt,
+                        float *out, hipStream_t s);
+// Workgroups of the batch kernel that fit on the device at once.
+int batch_grid_limit(int group, bool exact, int mask, int wpg);
+void *batch_kernel_fn(int group, bool exact, int mask);
+
+// Per-radius FP32 launchers, each defined in its own instantiation unit.
+template <int R>
+hipError_t launch_f32_radius(int var, bool exact, const float *in, const float *fa, const float *fb, float *out,
+                             int h, int w, int by, int wpg, hipStream_t s);
+#define PF_DECL_RADIUS(R)                                                                                  \
+    template <>                                                                                            \
+    hipError_t launch_f32_radius<R>(int var, bool exact, const float *in, const float *fa, const float *fb, \
+                                    float *out, int h, int w, int by, int wpg, hipStream_t s);
+PF_DECL_RADIUS(0)
+PF_DECL_RADIUS(1)
+PF_DECL_RADIUS(2)
+PF_DECL_RADIUS(3)
+PF_DECL_RADIUS(4)
+PF_DECL_RADIUS(5)
+PF_DECL_RADIUS(6)
+PF_DECL_RADIUS(7)
+PF_DECL_RADIUS(8)
+#undef PF_DECL_RADIUS
+
+// Batch kernels per (radius group, exact, variant mask), each in its own
+// unit. Masks: bit v for variant v; group 0 has masks 2 (separable only),
+// 3 (direct + separable) and 7 (all); group 1 has mask 3.
+template <int G, int E, int M>
+void *batch_fn();
+template <int G, int E, int M>
+hipError_t launch_batch_g(const BatchImg *imgs, const int32_t *task_img, int ntasks, int grid, int wpg,
+                          const float *in, const float *filt, float *out, hipStream_t s);
+#define PF_DECL_BATCH(G, E, M)                                                                                 \
+    template <>                                                                                                \
+    void *batch_fn<G, E, M>();                                                                                 \
+    template <>                                                                                                \
+    hipError_t launch_batch_g<G, E, M>(const BatchImg *imgs, const int32_t *task_img, int ntasks, int grid,     \
+                                       int wpg, const float *in, const float *filt, float *out, hipStream_t s);
+PF_DECL_BATCH(0, 0, 2)
+PF_DECL_BATCH(0, 1, 2)
+PF_DECL_BATCH(0, 0, 3)
+PF_DECL_BATCH(0, 1, 3)
+PF_DECL_BATCH(0, 0, 7)
+PF_DECL_BATCH(0, 1, 7)
+PF_DECL_BATCH(1, 0, 3)
+PF_DECL_BATCH(1, 1, 3)
+#undef PF_DECL_BATCH
+
+// Smallest compiled variant mask of a group that covers `used` (bit v set
+// if some image runs variant v).
+inline int batch_mask(int group, int used) {
+    if (group == 1) return 3;
+    if ((used & ~2) == 0) return 2;
+    if ((used & ~3) == 0) return 3;
+    return 7;
+}
+
+// Tune table lookup (tune.cpp).
+pf_tune_entry tune_lookup(int kind, int r, int64_t pixels);
+
+bool valid_shape(int by, int wpg);
+
+}  // namespace pf

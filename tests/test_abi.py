@@ -1,0 +1,155 @@
+"""The C ABI on the CPU: the library loads, exports every function that
+include/pf.h declares, and rejects invalid arguments before touching the
+device (host-side validation only; no compute call runs here)."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+import paper_1302_5586_amd as pf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pf_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pf.LIB_PATH):
+        from paper_1302_5586_amd import build as b
+        b.build()
+    return pf.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding knows a signature for each of them
+    assert set(names) <= set(pf._SIGS), set(names) - set(pf._SIGS)
+
+
+def test_status_strings(lib):
+    assert lib.pf_status_str(pf.PF_OK) == b"PF_OK"
+    assert lib.pf_status_str(pf.PF_EALIAS) == b"PF_EALIAS"
+    assert lib.pf_status_str(99) == b"PF_UNKNOWN"
+    assert b"gfx950" in lib.pf_version()
+
+
+FAKE = 1 << 40  # a 4-byte aligned address that validation never dereferences
+
+
+@pytest.mark.parametrize("h,w,r,inp,out,status", [
+    (0, 5, 1, FAKE, FAKE + (1 << 20), pf.PF_EINVAL),          # empty image
+    (5, -1, 1, FAKE, FAKE + (1 << 20), pf.PF_EINVAL),         # negative width
+    (5, 5, 9, FAKE, FAKE + (1 << 20), pf.PF_EINVAL),          # radius above PF_R_MAX
+    (5, 5, -1, FAKE, FAKE + (1 << 20), pf.PF_EINVAL),         # negative radius
+    (5, 5, 1, 0, FAKE, pf.PF_EINVAL),                         # null input
+    (5, 5, 1, FAKE + 2, FAKE + (1 << 20), pf.PF_EINVAL),      # misaligned
+    (5, 5, 1, FAKE, FAKE, pf.PF_EALIAS),                      # in place
+    (5, 5, 1, FAKE, FAKE + 4 * 24, pf.PF_EALIAS),             # partial overlap
+])
+def test_filter2d_validation(lib, h, w, r, inp, out, status):
+    got = lib.pf_filter2d_f32(h, w, r, inp, FAKE + (1 << 30), out, 0, None)
+    assert got == status
+    assert lib.pf_last_error() != b""
+
+
+def test_filter_flags_and_filter_alias(lib):
+    assert lib.pf_filter2d_f32(4, 4, 1, FAKE, FAKE + 4096, FAKE + (1 << 20), 0x80, None) == pf.PF_EINVAL
+    # filter overlapping the output
+    assert lib.pf_filter2d_f32(4, 4, 1, FAKE, FAKE + (1 << 20) + 8, FAKE + (1 << 20), 0, None) == pf.PF_EALIAS
+    assert lib.pf_filter_sep_f32(4, 4, 1, FAKE, 0, FAKE + 64, FAKE + (1 << 20), 0, None) == pf.PF_EINVAL
+    assert lib.pf_filter_f32_shaped(4, 4, 1, pf.KIND_2D, pf.VAR_SEPARABLE, 16, 4, FAKE, FAKE + 4096,
+                                    FAKE + (1 << 20), 0, None) == pf.PF_EINVAL
+    assert lib.pf_filter_f32_shaped(4, 4, 1, pf.KIND_2D, pf.VAR_DIRECT, 12, 4, FAKE, FAKE + 4096,
+                                    FAKE + (1 << 20), 0, None) == pf.PF_EINVAL
+
+
+def test_u8_validation(lib):
+    ok = dict(c=3, h=4, w=4, r=1, shift=6)
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.pf_filter2d_u8(a["c"], a["h"], a["w"], a["r"], a["shift"], a.get("inp", FAKE),
+                                  FAKE + 4096, a.get("out", FAKE + (1 << 20)), a.get("flags", 0), None)
+    assert call(c=0) == pf.PF_EINVAL
+    assert call(shift=32) == pf.PF_EINVAL
+    assert call(shift=-1) == pf.PF_EINVAL
+    assert call(flags=1) == pf.PF_EINVAL
+    assert call(out=FAKE + 10) == pf.PF_EALIAS
+    assert call(inp=0) == pf.PF_EINVAL
+
+
+def test_tune_table_roundtrip(lib, tmp_path):
+    pf.tune_reset()
+    e = pf.tune_lookup(pf.KIND_SEP, 2, 4096 * 4096)
+    assert e.variant == pf.VAR_SEPARABLE and e.size_class == 2
+    new = pf.TuneEntry(kind=pf.KIND_2D, r=1, size_class=0, variant=pf.VAR_DIRECT, rows_per_wave=64,
+                       waves_per_group=2, us=1.5)
+    pf.tune_set([new])
+    assert pf.tune_lookup(pf.KIND_2D, 1, 100).rows_per_wave == 64
+    path = str(tmp_path / "tune.json")
+    pf.tune_save(path)
+    doc = json.load(open(path))
+    assert len(doc["entries"]) == 3 * 9 * 3
+    pf.tune_reset()
+    assert pf.tune_lookup(pf.KIND_2D, 1, 100).rows_per_wave != 64
+    pf.tune_load(path)
+    got = pf.tune_lookup(pf.KIND_2D, 1, 100)
+    assert (got.rows_per_wave, got.waves_per_group) == (64, 2)
+    with pytest.raises(pf.PFInvalid):
+        pf.tune_set([pf.TuneEntry(kind=pf.KIND_SEP, r=3, size_class=0, variant=pf.VAR_SEP_DIRECT,
+                                  rows_per_wave=16, waves_per_group=4)])
+    with pytest.raises(pf.PFInvalid):
+        pf.tune_set([pf.TuneEntry(kind=pf.KIND_2D, r=1, size_class=0, variant=pf.VAR_DIRECT,
+                                  rows_per_wave=12, waves_per_group=4)])
+    pf.tune_reset()
+
+
+def _arr(t, vals):
+    a = (t * len(vals))(*vals)
+    return ctypes.cast(a, ctypes.c_void_p), a
+
+
+def test_batch_plan_validation(lib):
+    P = ctypes.c_void_p()
+    def create(h, w, r, kind, po, fo, npix, nfilt, flags=0):
+        keep = []
+        args = []
+        for t, v in ((ctypes.c_int32, h), (ctypes.c_int32, w), (ctypes.c_int32, r), (ctypes.c_int32, kind),
+                     (ctypes.c_int64, po), (ctypes.c_int64, fo)):
+            p, a = _arr(t, v)
+            keep.append(a)
+            args.append(p)
+        return lib.pf_batch_plan_create(len(h), *args, npix, nfilt, flags, ctypes.byref(P))
+    assert create([4], [4], [1], [0], [1], [0], 16, 9) == pf.PF_EINVAL        # image past the arena
+    assert create([4], [4], [1], [0], [0], [1], 16, 9) == pf.PF_EINVAL        # filter past the arena
+    assert create([4], [4], [1], [5], [0], [0], 16, 9) == pf.PF_EINVAL        # unknown kind
+    assert create([4, 4], [4, 4], [1, 1], [0, 0], [0, 8], [0, 0], 64, 9) == pf.PF_EALIAS   # overlapping images
+    assert create([4], [4], [1], [0], [0], [0], 16, 9, flags=0x100) == pf.PF_EINVAL
+    assert lib.pf_batch_plan_create(0, None, None, None, None, None, None, 1, 1, 0, ctypes.byref(P)) == pf.PF_EINVAL
+    assert lib.pf_batch_plan_destroy(None) == pf.PF_OK
+
+
+def test_server_validation(lib):
+    S = ctypes.c_void_p()
+    assert lib.pf_server_create(100, 2, 8, 16, 0, ctypes.byref(S)) == pf.PF_EINVAL     # budget too small
+    assert lib.pf_server_create(1 << 20, 0, 8, 16, 0, ctypes.byref(S)) == pf.PF_EINVAL  # no streams
+    assert lib.pf_server_create(1 << 20, 2, 0, 16, 0, ctypes.byref(S)) == pf.PF_EINVAL  # empty batches
+    assert lib.pf_server_create(1 << 20, 2, 8, 0, 0, ctypes.byref(S)) == pf.PF_EINVAL   # no queue
+    assert lib.pf_server_destroy(None) == pf.PF_OK
+
+
+def test_binding_rejects_host_tensors():
+    torch = pytest.importorskip("torch")
+    x = torch.zeros(4, 4)
+    with pytest.raises(ValueError):
+        pf.filter2d(x, torch.zeros(3, 3))

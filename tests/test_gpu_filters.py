@@ -1,0 +1,173 @@
+"""Parity of the HIP single-image filters with the oracle (GPU).
+
+FP32: every element within 1e-5 * sum(|w| |x|) of the oracle (see
+gpu_util), and bit-identical to the oracle with the exact flag. uint8:
+bit-exact. Shapes span several wave strips (248 columns for r <= 4, 240
+above) and several row tiles, with ragged tails, plus the degenerate
+shapes (1x1, one row, one column, images smaller than the window).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1302_5586_amd as pf
+import synth
+from gpu_util import assert_close, device, tolerance_2d, tolerance_sep
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1, 1), (1, 700), (700, 1), (3, 5), (37, 301), (129, 250), (64, 496), (257, 513)]
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _rand_filter(rng, r):
+    return rng.standard_normal((2 * r + 1, 2 * r + 1)).astype(np.float32)
+
+
+@pytest.mark.parametrize("r", range(0, 9))
+def test_2d_all_radii(r):
+    dev = device()
+    rng = np.random.default_rng(1000 + r)
+    f = _rand_filter(rng, r)
+    fd = _t(f, dev)
+    for h, w in SHAPES:
+        img = rng.random((h, w), dtype=np.float32)
+        ref = oracle.filter2d_f32(img, f)
+        got = pf.filter2d(_t(img, dev), fd).cpu().numpy()
+        assert_close(got, ref, tolerance_2d(img, f, r), "2d r=%d %dx%d" % (r, h, w))
+        exact = pf.filter2d(_t(img, dev), fd, exact=True).cpu().numpy()
+        assert np.array_equal(exact, ref), "exact 2d r=%d %dx%d differs from the oracle" % (r, h, w)
+
+
+@pytest.mark.parametrize("r", range(0, 9))
+def test_separable_all_radii(r):
+    dev = device()
+    rng = np.random.default_rng(2000 + r)
+    fx = rng.standard_normal(2 * r + 1).astype(np.float32)
+    fy = rng.standard_normal(2 * r + 1).astype(np.float32)
+    for h, w in SHAPES:
+        img = rng.random((h, w), dtype=np.float32)
+        ref = oracle.filter_sep_f32(img, fx, fy)
+        got = pf.filter_sep(_t(img, dev), _t(fx, dev), _t(fy, dev)).cpu().numpy()
+        assert_close(got, ref, tolerance_sep(img, fx, fy), "sep r=%d %dx%d" % (r, h, w))
+        exact = pf.filter_sep(_t(img, dev), _t(fx, dev), _t(fy, dev), exact=True).cpu().numpy()
+        assert np.array_equal(exact, ref), "exact sep r=%d %dx%d differs from the oracle" % (r, h, w)
+
+
+@pytest.mark.parametrize("r", [0, 1, 2])
+def test_separable_as_direct(r):
+    dev = device()
+    rng = np.random.default_rng(3000 + r)
+    fx = rng.random(2 * r + 1).astype(np.float32)
+    fy = rng.random(2 * r + 1).astype(np.float32)
+    both = _t(np.concatenate([fx, fy]), dev)
+    for h, w in SHAPES:
+        img = rng.random((h, w), dtype=np.float32)
+        ref = oracle.filter_sep_f32(img, fx, fy)
+        got = pf.filter_shaped(_t(img, dev), both, r, pf.KIND_SEP, pf.VAR_SEP_DIRECT, 16, 4).cpu().numpy()
+        assert_close(got, ref, tolerance_sep(img, fx, fy), "sep-as-2d r=%d %dx%d" % (r, h, w))
+
+
+@pytest.mark.parametrize("kind,var", [(0, 0), (1, 1), (1, 2)])
+def test_launch_shape_does_not_change_results(kind, var):
+    dev = device()
+    rng = np.random.default_rng(44)
+    r = 2
+    img = rng.random((300, 777), dtype=np.float32)
+    filt = rng.standard_normal(25 if kind == 0 else 10).astype(np.float32)
+    x, fd = _t(img, dev), _t(filt, dev)
+    outs = [pf.filter_shaped(x, fd, r, kind, var, by, wpg).cpu().numpy()
+            for by in (4, 8, 16, 32, 64, 128) for wpg in (1, 2, 4, 8)]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_config_small_2d():
+    dev = device()
+    cfg = synth.config_small()
+    ref = oracle.filter2d_f32(cfg.image, cfg.f2d)
+    got = pf.filter2d(_t(cfg.image, dev), _t(cfg.f2d, dev)).cpu().numpy()
+    err, rel = assert_close(got, ref, tolerance_2d(cfg.image, cfg.f2d, 1), "256x256 r=1")
+    print("256x256 r=1: max abs %.3g max rel %.3g" % (err, rel))
+
+
+def test_config_large_full():
+    """4096x4096, 5x5 Gaussian, as full 2D and as fused separable passes:
+    every output element against the oracle."""
+    dev = device()
+    cfg = synth.config_large()
+    x = _t(cfg.image, dev)
+    ref2 = oracle.filter2d_f32(cfg.image, cfg.f2d)
+    got2 = pf.filter2d(x, _t(cfg.f2d, dev)).cpu().numpy()
+    err, rel = assert_close(got2, ref2, tolerance_2d(cfg.image, cfg.f2d, 2), "4096^2 2d")
+    print("4096^2 2d: max abs %.3g max rel %.3g" % (err, rel))
+    refs = oracle.filter_sep_f32(cfg.image, cfg.f1d, cfg.f1d)
+    g = _t(cfg.f1d, dev)
+    gots = pf.filter_sep(x, g, g).cpu().numpy()
+    err, rel = assert_close(gots, refs, tolerance_sep(cfg.image, cfg.f1d, cfg.f1d), "4096^2 sep")
+    print("4096^2 sep: max abs %.3g max rel %.3g" % (err, rel))
+    # the two forms of the same Gaussian agree within both bounds
+    assert_close(gots, ref2, 2 * tolerance_2d(cfg.image, cfg.f2d, 2), "4096^2 sep vs 2d")
+
+
+@pytest.mark.parametrize("r", range(0, 9))
+def test_u8_all_radii(r):
+    dev = device()
+    rng = np.random.default_rng(4000 + r)
+    for (c, h, w) in [(1, 1, 1), (3, 1, 9), (2, 9, 1), (3, 37, 301), (2, 70, 250), (1, 33, 257), (3, 20, 1920)]:
+        for shift in (0, 6, 9):
+            img = rng.integers(0, 256, (c, h, w), dtype=np.uint8)
+            f = rng.integers(-8, 9, (2 * r + 1, 2 * r + 1)).astype(np.int8)
+            ref = oracle.filter2d_u8(img, f, shift)
+            got = pf.filter2d_u8(_t(img, dev), _t(f, dev), shift).cpu().numpy()
+            assert np.array_equal(got, ref), "u8 r=%d c=%d %dx%d shift=%d" % (r, c, h, w, shift)
+
+
+def test_u8_extreme_weights():
+    dev = device()
+    rng = np.random.default_rng(77)
+    for wv in (-128, 127):
+        img = rng.integers(0, 256, (1, 40, 300), dtype=np.uint8)
+        f = np.full((9, 9), wv, np.int8)
+        for shift in (0, 13, 31):
+            ref = oracle.filter2d_u8(img, f, shift)
+            got = pf.filter2d_u8(_t(img, dev), _t(f, dev), shift).cpu().numpy()
+            assert np.array_equal(got, ref)
+
+
+def test_config_rgb_full():
+    """1920x1080 planar RGB, 7x7 int8 weights, shift 6: bit-exact, every pixel."""
+    dev = device()
+    cfg = synth.config_rgb()
+    ref = oracle.filter2d_u8(cfg.image, cfg.filt, cfg.shift)
+    got = pf.filter2d_u8(_t(cfg.image, dev), _t(cfg.filt, dev), cfg.shift).cpu().numpy()
+    assert np.array_equal(got, ref)
+
+
+def test_determinism_and_nan():
+    dev = device()
+    rng = np.random.default_rng(5)
+    img = rng.random((123, 456), dtype=np.float32)
+    img[60, 200] = np.nan
+    f = _rand_filter(rng, 2)
+    x, fd = _t(img, dev), _t(f, dev)
+    a = pf.filter2d(x, fd).cpu().numpy()
+    b = pf.filter2d(x, fd).cpu().numpy()
+    assert np.array_equal(a, b, equal_nan=True)
+    assert np.isnan(a[58:63, 198:203]).all()
+    assert not np.isnan(a[0, 0])
+
+
+def test_strided_views_rejected():
+    dev = device()
+    import torch
+    x = torch.zeros(16, 16, device=dev)[:, ::2]
+    with pytest.raises(ValueError):
+        pf.filter2d(x, torch.zeros(3, 3, device=dev))
+    y = torch.zeros(16, 16, device=dev)
+    with pytest.raises(pf.PFAlias):
+        pf.filter2d(y, torch.zeros(3, 3, device=dev), out=y)
