@@ -1,0 +1,164 @@
+"""Batch plans on the GPU: every image of a persistent launch against the
+oracle, and bit-identical to the single-image call with the same variant
+(variant choice depends only on kind, radius and size), with and without
+graph replay, across replays and re-pointed arenas."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1302_5586_amd as pf
+import synth
+from gpu_util import assert_close, device, tolerance_2d, tolerance_sep
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _mixed_batch(seed, n, hi=300, rmax=8):
+    """n images with mixed kinds, radii 0..rmax and ragged sizes."""
+    rng = np.random.default_rng(seed)
+    imgs, filts, kinds = [], [], []
+    for i in range(n):
+        h = int(rng.integers(1, hi))
+        w = int(rng.integers(1, hi))
+        r = int(rng.integers(0, rmax + 1))
+        k = int(rng.integers(0, 2))
+        imgs.append(rng.random((h, w), dtype=np.float32))
+        if k == pf.KIND_2D:
+            filts.append(rng.standard_normal((2 * r + 1) ** 2).astype(np.float32))
+        else:
+            filts.append(rng.standard_normal(2 * (2 * r + 1)).astype(np.float32))
+        kinds.append(k)
+    return imgs, filts, kinds
+
+
+def _oracle_and_tol(img, filt, kind, r):
+    k = 2 * r + 1
+    if kind == pf.KIND_2D:
+        f2 = filt.reshape(k, k)
+        return oracle.filter2d_f32(img, f2), tolerance_2d(img, f2, r)
+    fx, fy = filt[:k], filt[k:]
+    return oracle.filter_sep_f32(img, fx, fy), tolerance_sep(img, fx, fy)
+
+
+def _single(xi, fi, kind, r, var, dev):
+    """The single-image call with a given variant and default shape."""
+    if kind == pf.KIND_2D:
+        return pf.filter2d(xi, fi.view(2 * r + 1, 2 * r + 1))
+    if var == pf.VAR_SEPARABLE:
+        k = 2 * r + 1
+        return pf.filter_sep(xi, fi[:k], fi[k:])
+    return pf.filter_shaped(xi, fi, r, kind, var, 16, 4)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_mixed_batch_against_oracle_and_single(graph):
+    dev = device()
+    import torch
+    imgs, filts, kinds = _mixed_batch(11, 60)
+    pk = pf.pack_batch(imgs, filts, kinds)
+    x, fl = _t(pk.pixels, dev), _t(pk.filters, dev)
+    out = torch.full_like(x, float("nan"))
+    plan = pf.BatchPlan(pk.h, pk.w, pk.r, pk.kind, pk.pix_off, pk.filt_off, x.numel(), fl.numel(), graph=graph)
+    info = plan.info()
+    assert info["launches"] == (1 if pk.r.max() <= 4 or pk.r.min() > 4 else 2)
+    var = plan.variants()
+    plan.run(x, fl, out)
+    got = out.cpu().numpy()
+    for i in range(len(imgs)):
+        h, w, r, k = int(pk.h[i]), int(pk.w[i]), int(pk.r[i]), int(pk.kind[i])
+        gi = got[pk.pix_off[i]:pk.pix_off[i] + h * w].reshape(h, w)
+        ref, tol = _oracle_and_tol(imgs[i], filts[i], k, r)
+        assert_close(gi, ref, tol, "batch image %d (%dx%d r=%d kind=%d)" % (i, h, w, r, k))
+        xi = x[pk.pix_off[i]:pk.pix_off[i] + h * w].view(h, w)
+        fi = fl[pk.filt_off[i]:pk.filt_off[i] + filts[i].size]
+        alone = _single(xi, fi, k, r, int(var[i]), dev).cpu().numpy()
+        assert np.array_equal(alone, gi), "image %d differs between batch and single launch" % i
+    # padding between images is never written
+    mask = np.ones(got.size, bool)
+    for i in range(len(imgs)):
+        mask[pk.pix_off[i]:pk.pix_off[i] + int(pk.h[i]) * int(pk.w[i])] = False
+    assert np.isnan(got[mask]).all()
+
+
+def test_graph_replay_and_repoint():
+    dev = device()
+    import torch
+    imgs, filts, kinds = _mixed_batch(12, 25, hi=200, rmax=4)
+    pk = pf.pack_batch(imgs, filts, kinds)
+    x, fl = _t(pk.pixels, dev), _t(pk.filters, dev)
+    plan = pf.BatchPlan(pk.h, pk.w, pk.r, pk.kind, pk.pix_off, pk.filt_off, x.numel(), fl.numel(), graph=True)
+    ref_plan = pf.BatchPlan(pk.h, pk.w, pk.r, pk.kind, pk.pix_off, pk.filt_off, x.numel(), fl.numel(), graph=False)
+    want = torch.empty_like(x)
+    ref_plan.run(x, fl, want)
+    want = want.cpu().numpy()
+    outs = [torch.zeros_like(x) for _ in range(3)]
+    for rep in range(3):
+        for o in outs:
+            o.zero_()
+            plan.run(x, fl, o)      # new arena pointer on each call: node re-pointed
+            torch.cuda.synchronize()
+            assert np.array_equal(o.cpu().numpy(), want), "replay %d" % rep
+    # a different input arena through the same graph
+    x2 = x * 2
+    o2 = torch.empty_like(x)
+    plan.run(x2, fl, o2)
+    ref_plan.run(x2, fl, outs[0])
+    assert np.array_equal(o2.cpu().numpy(), outs[0].cpu().numpy())
+
+
+def test_exact_batch_matches_oracle_bitwise():
+    dev = device()
+    import torch
+    imgs, filts, kinds = _mixed_batch(13, 20, hi=150, rmax=8)
+    pk = pf.pack_batch(imgs, filts, kinds)
+    x, fl = _t(pk.pixels, dev), _t(pk.filters, dev)
+    out = torch.empty_like(x)
+    plan = pf.BatchPlan(pk.h, pk.w, pk.r, pk.kind, pk.pix_off, pk.filt_off, x.numel(), fl.numel(), exact=True)
+    plan.run(x, fl, out)
+    got = out.cpu().numpy()
+    for i in range(len(imgs)):
+        h, w, r, k = int(pk.h[i]), int(pk.w[i]), int(pk.r[i]), int(pk.kind[i])
+        ref, _ = _oracle_and_tol(imgs[i], filts[i], k, r)
+        assert np.array_equal(got[pk.pix_off[i]:pk.pix_off[i] + h * w].reshape(h, w), ref), i
+
+
+def test_config_batch_512():
+    """The 512-image batch (seed 3): every image bit-identical to its single
+    launch; a sample of 40 images against the oracle element by element; and
+    the full batch against the oracle on sampled pixels of every image."""
+    dev = device()
+    import torch
+    b = synth.config_batch()
+    filts = [np.concatenate([b.fx[i], b.fx[i]]) for i in range(b.n)]
+    pk = pf.pack_batch(b.images, filts, [pf.KIND_SEP] * b.n)
+    x, fl = _t(pk.pixels, dev), _t(pk.filters, dev)
+    out = torch.empty_like(x)
+    plan = pf.BatchPlan(pk.h, pk.w, pk.r, pk.kind, pk.pix_off, pk.filt_off, x.numel(), fl.numel(), graph=True)
+    plan.run(x, fl, out)
+    plan.run(x, fl, out)
+    var = plan.variants()
+    got = out.cpu().numpy()
+    rng = np.random.default_rng(0)
+    for i in range(b.n):
+        h, w, r = int(pk.h[i]), int(pk.w[i]), int(pk.r[i])
+        gi = got[pk.pix_off[i]:pk.pix_off[i] + h * w].reshape(h, w)
+        xi = x[pk.pix_off[i]:pk.pix_off[i] + h * w].view(h, w)
+        fi = fl[pk.filt_off[i]:pk.filt_off[i] + 2 * (2 * r + 1)]
+        alone = _single(xi, fi, pf.KIND_SEP, r, int(var[i]), dev).cpu().numpy()
+        assert np.array_equal(alone, gi), i
+        if i % 13 == 0:
+            ref, tol = _oracle_and_tol(b.images[i], filts[i], pf.KIND_SEP, r)
+            assert_close(gi, ref, tol, "batch512 image %d" % i)
+        else:
+            # sampled pixels, including the four corners, against the 2D oracle
+            f2 = synth.outer_2d(b.fx[i], b.fx[i])
+            ys = np.concatenate([[0, 0, h - 1, h - 1], rng.integers(0, h, 12)])
+            xs = np.concatenate([[0, w - 1, 0, w - 1], rng.integers(0, w, 12)])
+            for y, xx in zip(ys, xs):
+                o = float(oracle.filter2d_f32_at(b.images[i], f2, r, int(y), int(xx)))
+                assert abs(float(gi[y, xx]) - o) <= 2e-5 * abs(o) + 1e-30, (i, y, xx)
