@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--cpu-sample-stride", type=int, default=16)
     ap.add_argument("--tune", default=os.path.join(ROOT, "paper_1302_5586_amd", "tune_mi355x.json"))
     ap.add_argument("--skip", default="", help="comma list of sections to skip: plain,large,rgb,serve,cpu")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 512 MiB device copy 4 times (reference for counter scaling)")
     return ap.parse_args()
 
 
@@ -86,6 +88,17 @@ def main():
     if os.path.exists(args.tune):
         pf.tune_load(args.tune)
         log("tune table: %s" % args.tune)
+
+    if args.calibrate_copy:
+        # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
+        # scale the counters of the filter kernels to bytes.
+        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 4 x %d bytes read and written" % (src.numel() * 4))
+        del src, dst
 
     # ---- batch workload (512 images, seed 3) --------------------------------
     t0 = time.time()
