@@ -20,7 +20,9 @@ from typing import Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpencilfilter.so")
+# PENCILFILTER_LIB selects another build of the same library (a variant
+# built with different compile-time options).
+LIB_PATH = os.environ.get("PENCILFILTER_LIB") or os.path.join(_HERE, "libpencilfilter.so")
 
 PF_OK, PF_EINVAL, PF_EALIAS, PF_EUNSUPPORTED, PF_EDEVICE, PF_ENOMEM, PF_EBUDGET, PF_EAGAIN, PF_ETIMEDOUT = range(9)
 PF_R_MAX = 8

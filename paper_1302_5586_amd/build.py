@@ -50,9 +50,10 @@ def _jobs():
     return out
 
 
-def _compile(job, verbose: bool) -> str:
+def _compile(job, verbose: bool, objdir: str = OBJDIR, extra=()) -> str:
     src, tag, defs = job
-    obj = os.path.join(OBJDIR, os.path.basename(src) + (("." + tag) if tag else "") + ".o")
+    defs = list(defs) + list(extra)
+    obj = os.path.join(objdir, os.path.basename(src) + (("." + tag) if tag else "") + ".o")
     t0 = time.time()
     if src.endswith(".hip"):
         cmd = [HIPCC, "-x", "hip", *DEVICE, *COMMON, *defs, "-c", src, "-o", obj]
@@ -73,16 +74,19 @@ def _compile(job, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
-    """Compile every source and link the shared library; returns its path."""
-    os.makedirs(OBJDIR, exist_ok=True)
+def build(verbose: bool = False, jobs: int = 0, defines=(), out: str = LIB) -> str:
+    """Compile every source and link the shared library; returns its path.
+    ``defines`` (e.g. ["-DPF_STRIP_ALIGNED=0"]) and ``out`` build a variant
+    of the library elsewhere, in its own object directory."""
+    objdir = OBJDIR if not defines else OBJDIR + "_" + "_".join(d.lstrip("-D").replace("=", "") for d in defines)
+    os.makedirs(objdir, exist_ok=True)
     work = _jobs()
     # big units first so the pool drains evenly
     work.sort(key=lambda j: (not j[0].endswith(".hip"), -len(j[1])))
     jobs = jobs or min(os.cpu_count() or 8, 16, len(work))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda j: _compile(j, verbose), work))
-    tmp = LIB + ".tmp%d" % os.getpid()
+        objs = list(ex.map(lambda j: _compile(j, verbose, objdir, defines), work))
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, *DEVICE, "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -90,9 +94,11 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("link failed")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    defs = [a for a in sys.argv[1:] if a.startswith("-D")]
+    outs = [a[len("--out="):] for a in sys.argv[1:] if a.startswith("--out=")]
+    print(build(verbose="-v" in sys.argv, defines=defs, out=outs[0] if outs else LIB))

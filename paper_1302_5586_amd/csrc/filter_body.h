@@ -68,6 +68,14 @@ __device__ __forceinline__ float from_left(float v) {
 __device__ __forceinline__ float from_right(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
+// The same shifts with an explicit value for the lane that has no source
+// lane (lane 0 for from_left, lane 63 for from_right).
+__device__ __forceinline__ float from_left_or(float old, float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_right_or(float old, float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
 __device__ __forceinline__ int from_left_i(int v) {
     return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
 }
@@ -125,6 +133,79 @@ __device__ __forceinline__ void store4(float *__restrict__ row, int xs, int w, c
 
 // ---------------------------------------------------------------- FP32 ---
 
+// One input row as a lane holds it: its 4 columns and, for an aligned
+// strip, R halo values: lane 0 holds columns x0-R .. x0-1 (just left of the
+// strip), lane 63 columns x0+256 .. x0+255+R (just right of it); the other
+// lanes' halo values are loaded but unused. Lanes 0 and 63 hand them to the
+// DPP shifts as the value for the lane that has no source lane.
+template <int R>
+struct RowF32 {
+    float v[4];
+    float hv[aligned_strip(R) ? R : 1];
+};
+
+typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+typedef float f3u __attribute__((ext_vector_type(3), aligned(4)));
+
+// N consecutive floats from a 4-byte aligned address as one vector load.
+template <int N>
+__device__ __forceinline__ void loadn(const float *__restrict__ p, float (&o)[N]) {
+    if constexpr (N == 4) {
+        const f4u q = *reinterpret_cast<const f4u *>(p);
+        o[0] = q.x, o[1] = q.y, o[2] = q.z, o[3] = q.w;
+    } else if constexpr (N == 3) {
+        const f3u q = *reinterpret_cast<const f3u *>(p);
+        o[0] = q.x, o[1] = q.y, o[2] = q.z;
+    } else if constexpr (N == 2) {
+        const f2u q = *reinterpret_cast<const f2u *>(p);
+        o[0] = q.x, o[1] = q.y;
+    } else {
+        o[0] = p[0];
+    }
+}
+
+// Load one row for a lane. FAST: the strip lies inside the image, so the
+// lane's 4 columns and its halo values are unconditional vector loads (no
+// divergence, so the wait counters stay exact across the pipelined chunk
+// loads); a strip flush with the left or right image edge takes its halo
+// from its own edge column. Otherwise every column is clamped to [0, w-1].
+template <int R, bool FAST>
+__device__ __forceinline__ void load_row(const float *__restrict__ row, int xs, int x0, int w, int lane,
+                                         RowF32<R> &q) {
+    if constexpr (FAST) {
+        const f4u t = *reinterpret_cast<const f4u *>(row + xs);
+        q.v[0] = t.x;
+        q.v[1] = t.y;
+        q.v[2] = t.z;
+        q.v[3] = t.w;
+    } else {
+        load4(row, xs, w, q.v);
+    }
+    if constexpr (aligned_strip(R)) {
+        const bool left = lane < kLanes / 2;
+        if constexpr (FAST) {
+            const int xh = left ? max(x0 - R, 0) : min(x0 + 4 * kLanes, w - R);
+            loadn<R>(row + xh, q.hv);
+            const bool edge = left ? (x0 == 0) : (x0 + 4 * kLanes == w);
+            const float e = left ? q.v[0] : q.v[3];
+#pragma unroll
+            for (int j = 0; j < R; ++j) q.hv[j] = edge ? e : q.hv[j];
+        } else {
+            const int xh = left ? x0 - R : x0 + 4 * kLanes;
+#pragma unroll
+            for (int j = 0; j < R; ++j) q.hv[j] = row[clampi(xh + j, 0, w - 1)];
+        }
+    }
+}
+
+// The branch-free path needs all 256 columns inside the image and the R
+// columns to the right either inside it too or entirely absent.
+template <int R>
+__device__ __forceinline__ bool fast_strip(int x0, int w) {
+    const int end = x0 + 4 * kLanes;
+    return end <= w && (end == w || end + R <= w);
+}
+
 template <int R, int VAR>
 struct Weights {
     static constexpr int K = 2 * R + 1;
@@ -160,16 +241,26 @@ struct Weights {
 // Output j of the strip collects input rows j .. j+2R (dy = -R .. R) and
 // lives in ring slot j mod K.
 template <int R, int VAR, bool EXACT, int RES, int IPRO>
-__device__ __forceinline__ void fold_row_f32(const Weights<R, VAR> &wt, const float v[4],
+__device__ __forceinline__ void fold_row_f32(const Weights<R, VAR> &wt, const RowF32<R> &q,
                                              float (&acc)[2 * R + 1][4]) {
     constexpr int K = 2 * R + 1;
     constexpr int NB = halo_lanes(R);
     constexpr int C = 4 * NB;
     constexpr int NW = 4 * (2 * NB + 1);
+    const float *v = q.v;
+    // win[C + c] is column xs + c of this lane's row, c in [-4 NB, 4 NB + 4).
     float win[NW];
 #pragma unroll
     for (int k = 0; k < 4; ++k) win[C + k] = v[k];
-    {
+    if constexpr (aligned_strip(R)) {
+        // Only the R columns on each side are needed; lanes 0 and 63 take
+        // them from the strip's halo columns instead of a neighbour.
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            win[C - R + j] = from_left_or(q.hv[j], v[4 - R + j]);
+            win[C + 4 + j] = from_right_or(q.hv[j], v[j]);
+        }
+    } else {
         float l[4] = {v[0], v[1], v[2], v[3]};
         float r[4] = {v[0], v[1], v[2], v[3]};
 #pragma unroll
@@ -213,54 +304,141 @@ __device__ __forceinline__ void fold_row_f32(const Weights<R, VAR> &wt, const fl
     }
 }
 
-// Input rows [i0, i0 + K) of a strip, all present; i0 = 2R + q*K so row
-// i0 + s has ring residue (2R + s) mod K.
-template <int R, int VAR, bool EXACT>
-__device__ __forceinline__ void chunk_f32(const Weights<R, VAR> &wt, const float *__restrict__ in,
-                                          float *__restrict__ out, float (&acc)[2 * R + 1][4], int h,
-                                          int w, int xs, int y0, int rows, int i0, bool out_lane) {
+// Rows per pipelined chunk: a multiple of K (ring residues stay
+// compile-time constants) near PF_CHUNK rows.
+#ifndef PF_CHUNK
+#define PF_CHUNK 8
+#endif
+template <int R>
+constexpr int chunk_rows() {
     constexpr int K = 2 * R + 1;
-    float v[K][4];
+    return K * (PF_CHUNK / K > 0 ? PF_CHUNK / K : 1);
+}
+
+// Load input rows [i0, i0 + CH) of a strip. Rows past the strip's last
+// input row `last` repeat that row (a cache hit), so the loads of the next
+// chunk are issued without a branch: a branch around them would make the
+// wait counts at the join conservative and serialize the chunks.
+template <int R, int CH, bool FAST>
+__device__ __forceinline__ void load_chunk(const float *__restrict__ in, int h, int w, int xs, int x0, int lane,
+                                           int y0, int i0, int last, RowF32<R> (&v)[CH]) {
 #pragma unroll
-    for (int s = 0; s < K; ++s) {
-        const int yy = clampi(y0 - R + i0 + s, 0, h - 1);
-        load4(in + (int64_t)yy * w, xs, w, v[s]);
+    for (int s = 0; s < CH; ++s) {
+        const int yy = clampi(y0 - R + min(i0 + s, last), 0, h - 1);
+        load_row<R, FAST>(in + (int64_t)yy * w, xs, x0, w, lane, v[s]);
     }
-    static_for<0, K>([&](auto sc) {
+}
+
+// Store the 4 outputs of a lane in output row y.
+template <bool FAST>
+__device__ __forceinline__ void store_row(float *__restrict__ out, int w, int xs, int y, bool out_lane,
+                                          const float (&a)[4]) {
+    float *o = out + (int64_t)y * w;
+    if constexpr (FAST) {
+        f4u t;
+        t.x = a[0];
+        t.y = a[1];
+        t.z = a[2];
+        t.w = a[3];
+        *reinterpret_cast<f4u *>(o + xs) = t;
+    } else if (out_lane) {
+        store4(o, xs, w, a);
+    }
+}
+
+// Fold input rows [i0, i0 + CH) (all present) into the ring and store the
+// outputs they complete. i0 = 2R + q*CH, so row i0 + s has ring residue
+// (2R + s) mod K; the output completed by row i is i - 2R.
+template <int R, int VAR, bool EXACT, int CH, bool FAST>
+__device__ __forceinline__ void process_chunk(const Weights<R, VAR> &wt, const RowF32<R> (&v)[CH],
+                                              float (&acc)[2 * R + 1][4], float *__restrict__ out, int w, int xs,
+                                              int y0, int i0, bool out_lane) {
+    constexpr int K = 2 * R + 1;
+    static_for<0, CH>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
         constexpr int RES = (2 * R + s) % K;
         fold_row_f32<R, VAR, EXACT, RES, -1>(wt, v[s], acc);
-        const int j = i0 + s - 2 * R;  // output completed by this row
         constexpr int done = (RES + 1) % K;
-        if (j < rows && out_lane) store4(out + (int64_t)(y0 + j) * w, xs, w, acc[done]);
+        store_row<FAST>(out, w, xs, y0 + i0 + s - 2 * R, out_lane, acc[done]);
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[done][k] = 0.0f;
     });
 }
 
-// Up to K input rows from i0 (each only if present); i0 = OFF (mod K).
-// Used for the rows left after the last full chunk, and as the whole row
-// loop of the compact form for large radii.
-template <int R, int VAR, bool EXACT, int OFF>
-__device__ __forceinline__ void tail_f32(const Weights<R, VAR> &wt, const float *__restrict__ in,
-                                         float *__restrict__ out, float (&acc)[2 * R + 1][4], int h, int w,
-                                         int xs, int y0, int rows, int i0, int nin, bool out_lane) {
+// Up to K rows from i0 (each only if below nin), loaded one by one; i0 is
+// congruent to OFF modulo K. The tail of the pipelined loop, and (OFF = 0,
+// from row 0) the whole row loop of the compact form for large radii.
+template <int R, int VAR, bool EXACT, int OFF, bool FAST>
+__device__ __forceinline__ void rows_group_f32(const Weights<R, VAR> &wt, const float *__restrict__ in,
+                                               float *__restrict__ out, float (&acc)[2 * R + 1][4], int h, int w,
+                                               int xs, int x0, int lane, int y0, int rows, int i0, int nin,
+                                               bool out_lane) {
     constexpr int K = 2 * R + 1;
     static_for<0, K>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
         if (i0 + s < nin) {
             constexpr int RES = (OFF + s) % K;
-            float v[4];
+            RowF32<R> v;
             const int yy = clampi(y0 - R + i0 + s, 0, h - 1);
-            load4(in + (int64_t)yy * w, xs, w, v);
+            load_row<R, FAST>(in + (int64_t)yy * w, xs, x0, w, lane, v);
             fold_row_f32<R, VAR, EXACT, RES, -1>(wt, v, acc);
             const int j = i0 + s - 2 * R;
             constexpr int done = (RES + 1) % K;
-            if (j >= 0 && j < rows && out_lane) store4(out + (int64_t)(y0 + j) * w, xs, w, acc[done]);
+            if (j >= 0 && j < rows) store_row<FAST>(out, w, xs, y0 + j, out_lane, acc[done]);
 #pragma unroll
             for (int k = 0; k < 4; ++k) acc[done][k] = 0.0f;
         }
     });
+}
+
+// The row loop for radii 0..4: prologue rows 0..2R-1, then full chunks
+// of CH rows in two alternating register sets (the loads of one chunk are
+// in flight while the other is folded; no per-row branch inside the loop),
+// then the remaining rows in groups of K.
+template <int R, int VAR, bool EXACT, bool FAST>
+__device__ __forceinline__ void rows_pipelined_f32(const Weights<R, VAR> &wt, const float *__restrict__ in,
+                                                   float *__restrict__ out, float (&acc)[2 * R + 1][4], int h, int w,
+                                                   int xs, int x0, int lane, int y0, int rows, bool out_lane) {
+    constexpr int K = 2 * R + 1;
+    constexpr int CH = chunk_rows<R>();
+    const int nin = rows + 2 * R;
+    int i0 = 2 * R;
+    if (i0 + CH <= nin) {
+        RowF32<R> pv[2 * R > 0 ? 2 * R : 1];
+        if constexpr (R > 0) {
+#pragma unroll
+            for (int i = 0; i < 2 * R; ++i)
+                load_row<R, FAST>(in + (int64_t)clampi(y0 - R + i, 0, h - 1) * w, xs, x0, w, lane, pv[i]);
+        }
+        const int last = nin - 1;
+        RowF32<R> va[CH], vb[CH];
+        load_chunk<R, CH, FAST>(in, h, w, xs, x0, lane, y0, i0, last, va);
+        if constexpr (R > 0) {
+            // Prologue: input rows 0 .. 2R-1 complete no output.
+            static_for<0, 2 * R>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                fold_row_f32<R, VAR, EXACT, i % K, i>(wt, pv[i], acc);
+            });
+        }
+        for (;;) {
+            load_chunk<R, CH, FAST>(in, h, w, xs, x0, lane, y0, i0 + CH, last, vb);
+            process_chunk<R, VAR, EXACT, CH, FAST>(wt, va, acc, out, w, xs, y0, i0, out_lane);
+            i0 += CH;
+            if (i0 + CH > nin) break;
+            load_chunk<R, CH, FAST>(in, h, w, xs, x0, lane, y0, i0 + CH, last, va);
+            process_chunk<R, VAR, EXACT, CH, FAST>(wt, vb, acc, out, w, xs, y0, i0, out_lane);
+            i0 += CH;
+            if (i0 + CH > nin) break;
+        }
+    } else if constexpr (R > 0) {
+        // Too few rows for one chunk: the prologue rows one by one.
+        for (int i = 0; i < 2 * R; i += K)
+            rows_group_f32<R, VAR, EXACT, 0, FAST>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, i, 2 * R, out_lane);
+    }
+    // Rows left after the last full chunk; i0 = 2R (mod K).
+    for (; i0 < nin; i0 += K)
+        rows_group_f32<R, VAR, EXACT, (2 * R) % K, FAST>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, i0, nin,
+                                                          out_lane);
 }
 
 // One wave computes output rows [y0, y0 + rows) of columns [x0, x0 + strip
@@ -270,38 +448,31 @@ __device__ __forceinline__ void strip_f32(const float *__restrict__ in, const fl
                                           const float *__restrict__ fb, float *__restrict__ out, int h, int w,
                                           int x0, int y0, int rows, int lane) {
     constexpr int K = 2 * R + 1;
-    constexpr int NB = halo_lanes(R);
+    constexpr int IL = idle_lanes(R);
     const Weights<R, VAR> wt(fa, fb);
-    const int xs = x0 + 4 * (lane - NB);
-    const bool out_lane = (lane >= NB) && (lane < kLanes - NB) && (xs < w);
+    const int xs = x0 + 4 * (lane - IL);
+    const bool out_lane = (lane >= IL) && (lane < kLanes - IL) && (xs < w);
     float acc[K][4];
 #pragma unroll
     for (int s = 0; s < K; ++s)
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[s][k] = 0.0f;
 
-    const int nin = rows + 2 * R;
     if constexpr (R > 4) {
         // Compact form for large radii: one guarded copy of the K-row body
         // (the first 2R rows fold into outputs j < 0 that are never stored).
-        for (int i0 = 0; i0 < nin; i0 += K) tail_f32<R, VAR, EXACT, 0>(wt, in, out, acc, h, w, xs, y0, rows, i0, nin, out_lane);
+        const int nin = rows + 2 * R;
+        for (int i0 = 0; i0 < nin; i0 += K)
+            rows_group_f32<R, VAR, EXACT, 0, false>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, i0, nin, out_lane);
+    } else if constexpr (idle_lanes(R) == 0) {
+        // Interior strips (all 256 columns inside the image) take the
+        // branch-free path; the last strip of a row of strips may not.
+        if (fast_strip<R>(x0, w))
+            rows_pipelined_f32<R, VAR, EXACT, true>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, out_lane);
+        else
+            rows_pipelined_f32<R, VAR, EXACT, false>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, out_lane);
     } else {
-        if constexpr (R > 0) {
-            // Prologue: input rows 0 .. 2R-1 complete no output.
-            float v[2 * R][4];
-#pragma unroll
-            for (int i = 0; i < 2 * R; ++i) {
-                const int yy = clampi(y0 - R + i, 0, h - 1);
-                load4(in + (int64_t)yy * w, xs, w, v[i]);
-            }
-            static_for<0, 2 * R>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                fold_row_f32<R, VAR, EXACT, i % K, i>(wt, v[i], acc);
-            });
-        }
-        int i0 = 2 * R;
-        for (; i0 + K <= nin; i0 += K) chunk_f32<R, VAR, EXACT>(wt, in, out, acc, h, w, xs, y0, rows, i0, out_lane);
-        tail_f32<R, VAR, EXACT, (2 * R) % K>(wt, in, out, acc, h, w, xs, y0, rows, i0, nin, out_lane);
+        rows_pipelined_f32<R, VAR, EXACT, false>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, out_lane);
     }
 }
 
@@ -466,12 +637,43 @@ __device__ __forceinline__ void store4_u8(uint8_t *__restrict__ row, int xs, int
     }
 }
 
+template <int R, int CH>
+__device__ __forceinline__ void load_chunk_u8(const uint8_t *__restrict__ in, int h, int w, bool aligned, int xs,
+                                              int y0, int i0, int last, uint32_t (&v)[CH]) {
+#pragma unroll
+    for (int s = 0; s < CH; ++s)
+        v[s] = load4_u8(in + (int64_t)clampi(y0 - R + min(i0 + s, last), 0, h - 1) * w, xs, w, aligned);
+}
+
+template <int R, int CH>
+__device__ __forceinline__ void process_chunk_u8(const WeightsU8<R> &wt, const uint32_t (&v)[CH],
+                                                 int (&acc)[2 * R + 1][4], uint8_t *__restrict__ out, int w,
+                                                 int shift, bool aligned, int xs, int y0, int rows, int i0, int nin,
+                                                 bool out_lane) {
+    constexpr int K = 2 * R + 1;
+    static_for<0, CH>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        if (i0 + s < nin) {
+            constexpr int RES = (2 * R + s) % K;
+            fold_row_u8<R, RES, -1>(wt, v[s], acc);
+            const int j = i0 + s - 2 * R;
+            constexpr int done = (RES + 1) % K;
+            if (j < rows && out_lane) store4_u8(out + (int64_t)(y0 + j) * w, xs, w, aligned, acc[done], wt.bias, shift);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[done][k] = 0;
+        }
+    });
+}
+
+// The uint8 strip walk: the same row ring and chunk pipelining as the FP32
+// strip, with 4 bytes per lane.
 template <int R>
 __device__ __forceinline__ void strip_u8(const uint8_t *__restrict__ in, const int8_t *__restrict__ filt,
                                          uint8_t *__restrict__ out, int h, int w, int shift, bool aligned,
                                          int x0, int y0, int rows, int lane) {
     constexpr int K = 2 * R + 1;
     constexpr int NB = halo_lanes(R);
+    constexpr int CH = K * (K >= 8 ? 1 : 8 / K);
     const WeightsU8<R> wt(filt);
     const int xs = x0 + 4 * (lane - NB);
     const bool out_lane = (lane >= NB) && (lane < kLanes - NB) && (xs < w);
@@ -480,45 +682,32 @@ __device__ __forceinline__ void strip_u8(const uint8_t *__restrict__ in, const i
     for (int s = 0; s < K; ++s)
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[s][k] = 0;
+    const int nin = rows + 2 * R;
+    const int last = nin - 1;
+    uint32_t pv[2 * R > 0 ? 2 * R : 1];
     if constexpr (R > 0) {
-        uint32_t v[2 * R];
 #pragma unroll
-        for (int i = 0; i < 2 * R; ++i) v[i] = load4_u8(in + (int64_t)clampi(y0 - R + i, 0, h - 1) * w, xs, w, aligned);
+        for (int i = 0; i < 2 * R; ++i) pv[i] = load4_u8(in + (int64_t)clampi(y0 - R + i, 0, h - 1) * w, xs, w, aligned);
+    }
+    uint32_t va[CH], vb[CH];
+    int i0 = 2 * R;
+    load_chunk_u8<R, CH>(in, h, w, aligned, xs, y0, i0, last, va);
+    if constexpr (R > 0) {
         static_for<0, 2 * R>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            fold_row_u8<R, i % K, i>(wt, v[i], acc);
+            fold_row_u8<R, i % K, i>(wt, pv[i], acc);
         });
     }
-    const int nin = rows + 2 * R;
-    int i0 = 2 * R;
-    for (; i0 + K <= nin; i0 += K) {
-        uint32_t v[K];
-#pragma unroll
-        for (int s = 0; s < K; ++s) v[s] = load4_u8(in + (int64_t)clampi(y0 - R + i0 + s, 0, h - 1) * w, xs, w, aligned);
-        static_for<0, K>([&](auto sc) {
-            constexpr int s = decltype(sc)::value;
-            constexpr int RES = (2 * R + s) % K;
-            fold_row_u8<R, RES, -1>(wt, v[s], acc);
-            const int j = i0 + s - 2 * R;
-            constexpr int done = (RES + 1) % K;
-            if (j < rows && out_lane) store4_u8(out + (int64_t)(y0 + j) * w, xs, w, aligned, acc[done], wt.bias, shift);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) acc[done][k] = 0;
-        });
+    for (;;) {
+        load_chunk_u8<R, CH>(in, h, w, aligned, xs, y0, i0 + CH, last, vb);
+        process_chunk_u8<R, CH>(wt, va, acc, out, w, shift, aligned, xs, y0, rows, i0, nin, out_lane);
+        i0 += CH;
+        if (i0 >= nin) break;
+        load_chunk_u8<R, CH>(in, h, w, aligned, xs, y0, i0 + CH, last, va);
+        process_chunk_u8<R, CH>(wt, vb, acc, out, w, shift, aligned, xs, y0, rows, i0, nin, out_lane);
+        i0 += CH;
+        if (i0 >= nin) break;
     }
-    static_for<0, K>([&](auto sc) {
-        constexpr int s = decltype(sc)::value;
-        if (i0 + s < nin) {
-            constexpr int RES = (2 * R + s) % K;
-            const uint32_t v = load4_u8(in + (int64_t)clampi(y0 - R + i0 + s, 0, h - 1) * w, xs, w, aligned);
-            fold_row_u8<R, RES, -1>(wt, v, acc);
-            const int j = i0 + s - 2 * R;
-            constexpr int done = (RES + 1) % K;
-            if (j < rows && out_lane) store4_u8(out + (int64_t)(y0 + j) * w, xs, w, aligned, acc[done], wt.bias, shift);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) acc[done][k] = 0;
-        }
-    });
 }
 
 template <int R>
@@ -535,7 +724,7 @@ __global__ __launch_bounds__(512) void k_filter_u8(const uint8_t *__restrict__ i
     const int sx = local / strips_y, sy = local - sx * strips_y;
     const int y0 = sy * by;
     const int64_t plane = (int64_t)p * h * w;
-    strip_u8<R>(in + plane, filt, out + plane, h, w, shift, aligned != 0, sx * strip_width(R), y0,
+    strip_u8<R>(in + plane, filt, out + plane, h, w, shift, aligned != 0, sx * strip_width_u8(R), y0,
                 min(by, h - y0), lane);
 }
 
@@ -581,7 +770,7 @@ hipError_t launch_f32_v(int var, const float *in, const float *fa, const float *
 template <int R>
 hipError_t launch_u8_t(const uint8_t *in, const int8_t *filt, uint8_t *out, int c, int h, int w, int shift, int by,
                        int wpg, hipStream_t s) {
-    const int sw = strip_width(R);
+    const int sw = strip_width_u8(R);
     const int strips_x = cdiv(w, sw), strips_y = cdiv(h, by);
     const int64_t per_plane = (int64_t)strips_x * strips_y;
     const int64_t ntasks64 = per_plane * c;

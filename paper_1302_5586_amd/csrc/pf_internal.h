@@ -11,10 +11,20 @@
 
 namespace pf {
 
-// Output columns one wave covers: 64 lanes of 4 columns, minus the halo
-// lanes on each side (one per 4 columns of radius).
+// A wave strip is 64 lanes x 4 columns. halo_lanes: neighbouring lanes on
+// each side whose columns a lane's window needs. For radii 1..4 every lane
+// produces outputs (256 columns, 1 KiB of FP32) and lanes 0 and 63 also
+// load the r columns beyond the strip; for larger radii the outermost
+// lanes only load halo columns and do not store.
+#ifndef PF_STRIP_ALIGNED
+#define PF_STRIP_ALIGNED 1
+#endif
 constexpr int halo_lanes(int r) { return (r + 3) / 4; }
-constexpr int strip_width(int r) { return 4 * (64 - 2 * halo_lanes(r)); }
+constexpr bool aligned_strip(int r) { return PF_STRIP_ALIGNED && r >= 1 && r <= 4; }
+constexpr int idle_lanes(int r) { return aligned_strip(r) ? 0 : halo_lanes(r); }
+constexpr int strip_width(int r) { return 4 * (64 - 2 * idle_lanes(r)); }
+// The uint8 strip keeps its halo lanes at every radius.
+constexpr int strip_width_u8(int r) { return 4 * (64 - 2 * halo_lanes(r)); }
 
 // One image of a batch as the persistent kernel sees it. `var` is the
 // executed variant (PF_VAR_*), `by` rows per wave tile, tasks are numbered
