@@ -46,6 +46,11 @@ typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 
 constexpr int kLanes = 64;
 
+// Word 3 of a raw buffer resource on gfx9-class parts (32-bit data format,
+// no swizzle, no stride): accesses at byte offsets >= num_records are
+// dropped on store and return 0 on load.
+constexpr int kBufferFlags = 0x00020000;
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -164,26 +169,54 @@ __device__ __forceinline__ void loadn(const float *__restrict__ p, float (&o)[N]
     }
 }
 
-// Load one row for a lane. FAST: the strip lies inside the image, so the
-// lane's 4 columns and its halo values are unconditional vector loads (no
-// divergence, so the wait counters stay exact across the pipelined chunk
-// loads); a strip flush with the left or right image edge takes its halo
-// from its own edge column. Otherwise every column is clamped to [0, w-1].
-template <int R, bool FAST>
+// How a strip loads its rows (chosen per strip, uniform over the wave):
+//   kFast: every lane's 4 columns lie inside the image (a halo lane left of
+//          column 0 aside): one 16-byte load per lane;
+//   kEdge: some columns lie outside; the lane loads the 4 in-bounds columns
+//          nearest to its own (w >= 4) and picks each clamped column from
+//          them;
+//   kTiny: images narrower than 4 columns: one clamped load per column.
+// All three are branch-free.
+constexpr int kFast = 0, kEdge = 1, kTiny = 2;
+
+__device__ __forceinline__ float pick4(const f4u &t, int i) {
+    return i == 0 ? t.x : (i == 1 ? t.y : (i == 2 ? t.z : t.w));
+}
+
+// Load one row for a lane: columns xs .. xs+3 clamped to [0, w-1], and for
+// an aligned strip the halo values (clamped too; in kFast a strip flush
+// with the image edge takes its halo from its own edge column).
+template <int R, int MODE>
 __device__ __forceinline__ void load_row(const float *__restrict__ row, int xs, int x0, int w, int lane,
                                          RowF32<R> &q) {
-    if constexpr (FAST) {
-        const f4u t = *reinterpret_cast<const f4u *>(row + xs);
-        q.v[0] = t.x;
-        q.v[1] = t.y;
-        q.v[2] = t.z;
-        q.v[3] = t.w;
+    if constexpr (MODE == kFast) {
+        if constexpr (idle_lanes(R) > 0) {
+            // The left halo lane of the first strip sits left of column 0.
+            const f4u t = *reinterpret_cast<const f4u *>(row + max(xs, 0));
+            const bool left_of_image = xs < 0;
+            q.v[0] = t.x;
+            q.v[1] = left_of_image ? t.x : t.y;
+            q.v[2] = left_of_image ? t.x : t.z;
+            q.v[3] = left_of_image ? t.x : t.w;
+        } else {
+            const f4u t = *reinterpret_cast<const f4u *>(row + xs);
+            q.v[0] = t.x;
+            q.v[1] = t.y;
+            q.v[2] = t.z;
+            q.v[3] = t.w;
+        }
+    } else if constexpr (MODE == kEdge) {
+        const int xa = clampi(xs, 0, w - 4);
+        const f4u t = *reinterpret_cast<const f4u *>(row + xa);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q.v[k] = pick4(t, clampi(xs + k, 0, w - 1) - xa);
     } else {
-        load4(row, xs, w, q.v);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q.v[k] = row[clampi(xs + k, 0, w - 1)];
     }
     if constexpr (aligned_strip(R)) {
         const bool left = lane < kLanes / 2;
-        if constexpr (FAST) {
+        if constexpr (MODE == kFast) {
             const int xh = left ? max(x0 - R, 0) : min(x0 + 4 * kLanes, w - R);
             loadn<R>(row + xh, q.hv);
             const bool edge = left ? (x0 == 0) : (x0 + 4 * kLanes == w);
@@ -198,12 +231,14 @@ __device__ __forceinline__ void load_row(const float *__restrict__ row, int xs, 
     }
 }
 
-// The branch-free path needs all 256 columns inside the image and the R
-// columns to the right either inside it too or entirely absent.
+// kFast needs every lane's columns to end inside the image; for an aligned
+// strip also the R columns to its right inside it, or none.
 template <int R>
 __device__ __forceinline__ bool fast_strip(int x0, int w) {
-    const int end = x0 + 4 * kLanes;
-    return end <= w && (end == w || end + R <= w);
+    constexpr int IL = idle_lanes(R);
+    const int end = x0 + 4 * (kLanes - IL);
+    if constexpr (aligned_strip(R)) return end <= w && (end == w || end + R <= w);
+    return end <= w;
 }
 
 template <int R, int VAR>
@@ -319,37 +354,56 @@ constexpr int chunk_rows() {
 // input row `last` repeat that row (a cache hit), so the loads of the next
 // chunk are issued without a branch: a branch around them would make the
 // wait counts at the join conservative and serialize the chunks.
-template <int R, int CH, bool FAST>
+template <int R, int CH, int MODE>
 __device__ __forceinline__ void load_chunk(const float *__restrict__ in, int h, int w, int xs, int x0, int lane,
                                            int y0, int i0, int last, RowF32<R> (&v)[CH]) {
 #pragma unroll
     for (int s = 0; s < CH; ++s) {
         const int yy = clampi(y0 - R + min(i0 + s, last), 0, h - 1);
-        load_row<R, FAST>(in + (int64_t)yy * w, xs, x0, w, lane, v[s]);
+        load_row<R, MODE>(in + (int64_t)yy * w, xs, x0, w, lane, v[s]);
     }
 }
 
-// Store the 4 outputs of a lane in output row y.
-template <bool FAST>
+// Store the 4 outputs of a lane in output row y, without a branch (so the
+// wait counts of the loads in flight stay exact). kFast with every lane an
+// output lane: one 16-byte store. kFast with halo lanes: one 16-byte store
+// through a buffer resource whose range is the row, halo lanes passing an
+// offset outside it (the hardware drops such accesses). Otherwise four
+// dword stores through that resource: columns at or beyond w are dropped.
+template <int MODE, int IL>
 __device__ __forceinline__ void store_row(float *__restrict__ out, int w, int xs, int y, bool out_lane,
                                           const float (&a)[4]) {
     float *o = out + (int64_t)y * w;
-    if constexpr (FAST) {
+    if constexpr (MODE == kFast && IL == 0) {
         f4u t;
         t.x = a[0];
         t.y = a[1];
         t.z = a[2];
         t.w = a[3];
         *reinterpret_cast<f4u *>(o + xs) = t;
-    } else if (out_lane) {
-        store4(o, xs, w, a);
+    } else if constexpr (MODE == kFast) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(o, 0, w * 4, kBufferFlags);
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        u4 t;
+        t.x = __float_as_uint(a[0]);
+        t.y = __float_as_uint(a[1]);
+        t.z = __float_as_uint(a[2]);
+        t.w = __float_as_uint(a[3]);
+        __builtin_amdgcn_raw_buffer_store_b128(t, rs, out_lane ? xs * 4 : 0x7ffffff0, 0, 0);
+    } else {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(o, 0, w * 4, kBufferFlags);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int off = out_lane ? (xs + k) * 4 : 0x7ffffff0;
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(a[k]), rs, off, 0, 0);
+        }
     }
 }
 
 // Fold input rows [i0, i0 + CH) (all present) into the ring and store the
 // outputs they complete. i0 = 2R + q*CH, so row i0 + s has ring residue
 // (2R + s) mod K; the output completed by row i is i - 2R.
-template <int R, int VAR, bool EXACT, int CH, bool FAST>
+template <int R, int VAR, bool EXACT, int CH, int MODE>
 __device__ __forceinline__ void process_chunk(const Weights<R, VAR> &wt, const RowF32<R> (&v)[CH],
                                               float (&acc)[2 * R + 1][4], float *__restrict__ out, int w, int xs,
                                               int y0, int i0, bool out_lane) {
@@ -359,7 +413,7 @@ __device__ __forceinline__ void process_chunk(const Weights<R, VAR> &wt, const R
         constexpr int RES = (2 * R + s) % K;
         fold_row_f32<R, VAR, EXACT, RES, -1>(wt, v[s], acc);
         constexpr int done = (RES + 1) % K;
-        store_row<FAST>(out, w, xs, y0 + i0 + s - 2 * R, out_lane, acc[done]);
+        store_row<MODE, idle_lanes(R)>(out, w, xs, y0 + i0 + s - 2 * R, out_lane, acc[done]);
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[done][k] = 0.0f;
     });
@@ -368,7 +422,7 @@ __device__ __forceinline__ void process_chunk(const Weights<R, VAR> &wt, const R
 // Up to K rows from i0 (each only if below nin), loaded one by one; i0 is
 // congruent to OFF modulo K. The tail of the pipelined loop, and (OFF = 0,
 // from row 0) the whole row loop of the compact form for large radii.
-template <int R, int VAR, bool EXACT, int OFF, bool FAST>
+template <int R, int VAR, bool EXACT, int OFF, int MODE>
 __device__ __forceinline__ void rows_group_f32(const Weights<R, VAR> &wt, const float *__restrict__ in,
                                                float *__restrict__ out, float (&acc)[2 * R + 1][4], int h, int w,
                                                int xs, int x0, int lane, int y0, int rows, int i0, int nin,
@@ -380,11 +434,11 @@ __device__ __forceinline__ void rows_group_f32(const Weights<R, VAR> &wt, const 
             constexpr int RES = (OFF + s) % K;
             RowF32<R> v;
             const int yy = clampi(y0 - R + i0 + s, 0, h - 1);
-            load_row<R, FAST>(in + (int64_t)yy * w, xs, x0, w, lane, v);
+            load_row<R, MODE>(in + (int64_t)yy * w, xs, x0, w, lane, v);
             fold_row_f32<R, VAR, EXACT, RES, -1>(wt, v, acc);
             const int j = i0 + s - 2 * R;
             constexpr int done = (RES + 1) % K;
-            if (j >= 0 && j < rows) store_row<FAST>(out, w, xs, y0 + j, out_lane, acc[done]);
+            if (j >= 0 && j < rows) store_row<MODE, idle_lanes(R)>(out, w, xs, y0 + j, out_lane, acc[done]);
 #pragma unroll
             for (int k = 0; k < 4; ++k) acc[done][k] = 0.0f;
         }
@@ -395,7 +449,7 @@ __device__ __forceinline__ void rows_group_f32(const Weights<R, VAR> &wt, const 
 // of CH rows in two alternating register sets (the loads of one chunk are
 // in flight while the other is folded; no per-row branch inside the loop),
 // then the remaining rows in groups of K.
-template <int R, int VAR, bool EXACT, bool FAST>
+template <int R, int VAR, bool EXACT, int MODE>
 __device__ __forceinline__ void rows_pipelined_f32(const Weights<R, VAR> &wt, const float *__restrict__ in,
                                                    float *__restrict__ out, float (&acc)[2 * R + 1][4], int h, int w,
                                                    int xs, int x0, int lane, int y0, int rows, bool out_lane) {
@@ -408,11 +462,11 @@ __device__ __forceinline__ void rows_pipelined_f32(const Weights<R, VAR> &wt, co
         if constexpr (R > 0) {
 #pragma unroll
             for (int i = 0; i < 2 * R; ++i)
-                load_row<R, FAST>(in + (int64_t)clampi(y0 - R + i, 0, h - 1) * w, xs, x0, w, lane, pv[i]);
+                load_row<R, MODE>(in + (int64_t)clampi(y0 - R + i, 0, h - 1) * w, xs, x0, w, lane, pv[i]);
         }
         const int last = nin - 1;
         RowF32<R> va[CH], vb[CH];
-        load_chunk<R, CH, FAST>(in, h, w, xs, x0, lane, y0, i0, last, va);
+        load_chunk<R, CH, MODE>(in, h, w, xs, x0, lane, y0, i0, last, va);
         if constexpr (R > 0) {
             // Prologue: input rows 0 .. 2R-1 complete no output.
             static_for<0, 2 * R>([&](auto ic) {
@@ -421,23 +475,23 @@ __device__ __forceinline__ void rows_pipelined_f32(const Weights<R, VAR> &wt, co
             });
         }
         for (;;) {
-            load_chunk<R, CH, FAST>(in, h, w, xs, x0, lane, y0, i0 + CH, last, vb);
-            process_chunk<R, VAR, EXACT, CH, FAST>(wt, va, acc, out, w, xs, y0, i0, out_lane);
+            load_chunk<R, CH, MODE>(in, h, w, xs, x0, lane, y0, i0 + CH, last, vb);
+            process_chunk<R, VAR, EXACT, CH, MODE>(wt, va, acc, out, w, xs, y0, i0, out_lane);
             i0 += CH;
             if (i0 + CH > nin) break;
-            load_chunk<R, CH, FAST>(in, h, w, xs, x0, lane, y0, i0 + CH, last, va);
-            process_chunk<R, VAR, EXACT, CH, FAST>(wt, vb, acc, out, w, xs, y0, i0, out_lane);
+            load_chunk<R, CH, MODE>(in, h, w, xs, x0, lane, y0, i0 + CH, last, va);
+            process_chunk<R, VAR, EXACT, CH, MODE>(wt, vb, acc, out, w, xs, y0, i0, out_lane);
             i0 += CH;
             if (i0 + CH > nin) break;
         }
     } else if constexpr (R > 0) {
         // Too few rows for one chunk: the prologue rows one by one.
         for (int i = 0; i < 2 * R; i += K)
-            rows_group_f32<R, VAR, EXACT, 0, FAST>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, i, 2 * R, out_lane);
+            rows_group_f32<R, VAR, EXACT, 0, MODE>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, i, 2 * R, out_lane);
     }
     // Rows left after the last full chunk; i0 = 2R (mod K).
     for (; i0 < nin; i0 += K)
-        rows_group_f32<R, VAR, EXACT, (2 * R) % K, FAST>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, i0, nin,
+        rows_group_f32<R, VAR, EXACT, (2 * R) % K, MODE>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, i0, nin,
                                                           out_lane);
 }
 
@@ -463,16 +517,18 @@ __device__ __forceinline__ void strip_f32(const float *__restrict__ in, const fl
         // (the first 2R rows fold into outputs j < 0 that are never stored).
         const int nin = rows + 2 * R;
         for (int i0 = 0; i0 < nin; i0 += K)
-            rows_group_f32<R, VAR, EXACT, 0, false>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, i0, nin, out_lane);
-    } else if constexpr (idle_lanes(R) == 0) {
-        // Interior strips (all 256 columns inside the image) take the
-        // branch-free path; the last strip of a row of strips may not.
-        if (fast_strip<R>(x0, w))
-            rows_pipelined_f32<R, VAR, EXACT, true>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, out_lane);
-        else
-            rows_pipelined_f32<R, VAR, EXACT, false>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, out_lane);
+            rows_group_f32<R, VAR, EXACT, 0, kTiny>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, i0, nin, out_lane);
     } else {
-        rows_pipelined_f32<R, VAR, EXACT, false>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, out_lane);
+        if (fast_strip<R>(x0, w)) {
+            rows_pipelined_f32<R, VAR, EXACT, kFast>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, out_lane);
+        } else if (w >= 4) {
+            rows_pipelined_f32<R, VAR, EXACT, kEdge>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, out_lane);
+        } else {
+            const int nin = rows + 2 * R;
+            for (int i0 = 0; i0 < nin; i0 += K)
+                rows_group_f32<R, VAR, EXACT, 0, kTiny>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, i0, nin,
+                                                        out_lane);
+        }
     }
 }
 
@@ -569,12 +625,29 @@ struct WeightsU8 {
     }
 };
 
-__device__ __forceinline__ uint32_t load4_u8(const uint8_t *__restrict__ row, int xs, int w, bool aligned) {
-    if (aligned && xs >= 0 && xs + 3 < w) return *reinterpret_cast<const uint32_t *>(row + xs);
-    uint32_t v = 0;
+// Bytes xs .. xs+3 of a row, clamped to [0, w-1], packed little-endian.
+// kFast (rows 4-byte aligned, every lane's bytes end inside the row): one
+// dword load, the halo lane left of byte 0 replicating byte 0. kEdge
+// (aligned rows, w >= 4): the nearest in-bounds dword, bytes picked from
+// it. kTiny (unaligned rows or w < 4): one clamped byte load per byte.
+template <int MODE>
+__device__ __forceinline__ uint32_t load_u8(const uint8_t *__restrict__ row, int xs, int w) {
+    if constexpr (MODE == kFast) {
+        const uint32_t t = *reinterpret_cast<const uint32_t *>(row + max(xs, 0));
+        return xs < 0 ? (t & 0xffu) * 0x01010101u : t;
+    } else if constexpr (MODE == kEdge) {
+        const int xa = clampi(xs, 0, w - 4);
+        const uint32_t t = *reinterpret_cast<const uint32_t *>(row + xa);
+        uint32_t v = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) v |= (uint32_t)row[clampi(xs + k, 0, w - 1)] << (8 * k);
-    return v;
+        for (int k = 0; k < 4; ++k) v |= ((t >> (8 * (clampi(xs + k, 0, w - 1) - xa))) & 0xffu) << (8 * k);
+        return v;
+    } else {
+        uint32_t v = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v |= (uint32_t)row[clampi(xs + k, 0, w - 1)] << (8 * k);
+        return v;
+    }
 }
 
 template <int R, int RES, int IPRO>
@@ -620,60 +693,132 @@ __device__ __forceinline__ void fold_row_u8(const WeightsU8<R> &wt, uint32_t own
     }
 }
 
-__device__ __forceinline__ void store4_u8(uint8_t *__restrict__ row, int xs, int w, bool aligned,
-                                          const int (&a)[4], int bias, int shift) {
+// Finish 4 outputs (add the bias back, arithmetic shift, saturate) and
+// store them through a buffer resource spanning the row: one dword store in
+// kFast, else four byte stores; bytes at or beyond w and halo lanes
+// (offset outside the range) are dropped by the hardware. No branch.
+template <int MODE>
+__device__ __forceinline__ void store_u8(uint8_t *__restrict__ row, int xs, int w, bool out_lane, const int (&a)[4],
+                                         int bias, int shift) {
     uint32_t pk = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int q = (a[k] + bias) >> shift;  // arithmetic shift of a signed int
-        pk |= (uint32_t)clampi(q, 0, 255) << (8 * k);
+        int q = clampi((a[k] + bias) >> shift, 0, 255);  // arithmetic shift of a signed int
+        // Keep each saturated byte opaque until it is packed: fused into the
+        // gfx950 packed shift-and-saturate instruction, the pair of bytes
+        // came back with the upper half of the dword not cleared, and the
+        // OR with bytes 2 and 3 then set them to 255.
+        asm volatile("" : "+v"(q));
+        pk |= (uint32_t)q << (8 * k);
     }
-    if (aligned && xs + 3 < w) {
-        *reinterpret_cast<uint32_t *>(row + xs) = pk;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(row, 0, w, kBufferFlags);
+    if constexpr (MODE == kFast) {
+        __builtin_amdgcn_raw_buffer_store_b32(pk, rs, out_lane ? xs : 0x7ffffff0, 0, 0);
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (xs + k < w) row[xs + k] = (uint8_t)(pk >> (8 * k));
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(pk >> (8 * k)), rs, out_lane ? xs + k : 0x7ffffff0, 0, 0);
     }
 }
 
-template <int R, int CH>
-__device__ __forceinline__ void load_chunk_u8(const uint8_t *__restrict__ in, int h, int w, bool aligned, int xs,
-                                              int y0, int i0, int last, uint32_t (&v)[CH]) {
+template <int R, int CH, int MODE>
+__device__ __forceinline__ void load_chunk_u8(const uint8_t *__restrict__ in, int h, int w, int xs, int y0, int i0,
+                                              int last, uint32_t (&v)[CH]) {
 #pragma unroll
-    for (int s = 0; s < CH; ++s)
-        v[s] = load4_u8(in + (int64_t)clampi(y0 - R + min(i0 + s, last), 0, h - 1) * w, xs, w, aligned);
+    for (int s = 0; s < CH; ++s) v[s] = load_u8<MODE>(in + (int64_t)clampi(y0 - R + min(i0 + s, last), 0, h - 1) * w, xs, w);
 }
 
-template <int R, int CH>
+// Fold rows [i0, i0 + CH) (all present; i0 = 2R + q*CH) and store the
+// outputs they complete.
+template <int R, int CH, int MODE>
 __device__ __forceinline__ void process_chunk_u8(const WeightsU8<R> &wt, const uint32_t (&v)[CH],
                                                  int (&acc)[2 * R + 1][4], uint8_t *__restrict__ out, int w,
-                                                 int shift, bool aligned, int xs, int y0, int rows, int i0, int nin,
-                                                 bool out_lane) {
+                                                 int shift, int xs, int y0, int i0, bool out_lane) {
     constexpr int K = 2 * R + 1;
     static_for<0, CH>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
+        constexpr int RES = (2 * R + s) % K;
+        fold_row_u8<R, RES, -1>(wt, v[s], acc);
+        constexpr int done = (RES + 1) % K;
+        store_u8<MODE>(out + (int64_t)(y0 + i0 + s - 2 * R) * w, xs, w, out_lane, acc[done], wt.bias, shift);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[done][k] = 0;
+    });
+}
+
+// Up to K rows from i0 (those below nin), loaded one by one; i0 = OFF
+// (mod K).
+template <int R, int OFF, int MODE>
+__device__ __forceinline__ void rows_group_u8(const WeightsU8<R> &wt, const uint8_t *__restrict__ in,
+                                              uint8_t *__restrict__ out, int (&acc)[2 * R + 1][4], int h, int w,
+                                              int shift, int xs, int y0, int rows, int i0, int nin, bool out_lane) {
+    constexpr int K = 2 * R + 1;
+    static_for<0, K>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
         if (i0 + s < nin) {
-            constexpr int RES = (2 * R + s) % K;
-            fold_row_u8<R, RES, -1>(wt, v[s], acc);
+            constexpr int RES = (OFF + s) % K;
+            const uint32_t v = load_u8<MODE>(in + (int64_t)clampi(y0 - R + i0 + s, 0, h - 1) * w, xs, w);
+            fold_row_u8<R, RES, -1>(wt, v, acc);
             const int j = i0 + s - 2 * R;
             constexpr int done = (RES + 1) % K;
-            if (j < rows && out_lane) store4_u8(out + (int64_t)(y0 + j) * w, xs, w, aligned, acc[done], wt.bias, shift);
+            if (j >= 0 && j < rows) store_u8<MODE>(out + (int64_t)(y0 + j) * w, xs, w, out_lane, acc[done], wt.bias, shift);
 #pragma unroll
             for (int k = 0; k < 4; ++k) acc[done][k] = 0;
         }
     });
 }
 
-// The uint8 strip walk: the same row ring and chunk pipelining as the FP32
-// strip, with 4 bytes per lane.
+// The uint8 row loop: prologue, full chunks in two alternating register
+// sets, then the remaining rows in groups of K (as the FP32 strip).
+template <int R, int MODE>
+__device__ __forceinline__ void rows_u8(const WeightsU8<R> &wt, const uint8_t *__restrict__ in,
+                                        uint8_t *__restrict__ out, int (&acc)[2 * R + 1][4], int h, int w, int shift,
+                                        int xs, int y0, int rows, bool out_lane) {
+    constexpr int K = 2 * R + 1;
+    constexpr int CH = K * (K >= 8 ? 1 : 8 / K);
+    const int nin = rows + 2 * R;
+    int i0 = 2 * R;
+    if (i0 + CH <= nin) {
+        const int last = nin - 1;
+        uint32_t pv[2 * R > 0 ? 2 * R : 1];
+        if constexpr (R > 0) {
+#pragma unroll
+            for (int i = 0; i < 2 * R; ++i) pv[i] = load_u8<MODE>(in + (int64_t)clampi(y0 - R + i, 0, h - 1) * w, xs, w);
+        }
+        uint32_t va[CH], vb[CH];
+        load_chunk_u8<R, CH, MODE>(in, h, w, xs, y0, i0, last, va);
+        if constexpr (R > 0) {
+            static_for<0, 2 * R>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                fold_row_u8<R, i % K, i>(wt, pv[i], acc);
+            });
+        }
+        for (;;) {
+            load_chunk_u8<R, CH, MODE>(in, h, w, xs, y0, i0 + CH, last, vb);
+            process_chunk_u8<R, CH, MODE>(wt, va, acc, out, w, shift, xs, y0, i0, out_lane);
+            i0 += CH;
+            if (i0 + CH > nin) break;
+            load_chunk_u8<R, CH, MODE>(in, h, w, xs, y0, i0 + CH, last, va);
+            process_chunk_u8<R, CH, MODE>(wt, vb, acc, out, w, shift, xs, y0, i0, out_lane);
+            i0 += CH;
+            if (i0 + CH > nin) break;
+        }
+    } else if constexpr (R > 0) {
+        for (int i = 0; i < 2 * R; i += K)
+            rows_group_u8<R, 0, MODE>(wt, in, out, acc, h, w, shift, xs, y0, rows, i, 2 * R, out_lane);
+    }
+    for (; i0 < nin; i0 += K)
+        rows_group_u8<R, (2 * R) % K, MODE>(wt, in, out, acc, h, w, shift, xs, y0, rows, i0, nin, out_lane);
+}
+
+// The uint8 strip walk: the row ring of the FP32 strip, 4 bytes per lane,
+// halo lanes on each side.
 template <int R>
 __device__ __forceinline__ void strip_u8(const uint8_t *__restrict__ in, const int8_t *__restrict__ filt,
                                          uint8_t *__restrict__ out, int h, int w, int shift, bool aligned,
                                          int x0, int y0, int rows, int lane) {
     constexpr int K = 2 * R + 1;
     constexpr int NB = halo_lanes(R);
-    constexpr int CH = K * (K >= 8 ? 1 : 8 / K);
     const WeightsU8<R> wt(filt);
     const int xs = x0 + 4 * (lane - NB);
     const bool out_lane = (lane >= NB) && (lane < kLanes - NB) && (xs < w);
@@ -682,32 +827,12 @@ __device__ __forceinline__ void strip_u8(const uint8_t *__restrict__ in, const i
     for (int s = 0; s < K; ++s)
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[s][k] = 0;
-    const int nin = rows + 2 * R;
-    const int last = nin - 1;
-    uint32_t pv[2 * R > 0 ? 2 * R : 1];
-    if constexpr (R > 0) {
-#pragma unroll
-        for (int i = 0; i < 2 * R; ++i) pv[i] = load4_u8(in + (int64_t)clampi(y0 - R + i, 0, h - 1) * w, xs, w, aligned);
-    }
-    uint32_t va[CH], vb[CH];
-    int i0 = 2 * R;
-    load_chunk_u8<R, CH>(in, h, w, aligned, xs, y0, i0, last, va);
-    if constexpr (R > 0) {
-        static_for<0, 2 * R>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            fold_row_u8<R, i % K, i>(wt, pv[i], acc);
-        });
-    }
-    for (;;) {
-        load_chunk_u8<R, CH>(in, h, w, aligned, xs, y0, i0 + CH, last, vb);
-        process_chunk_u8<R, CH>(wt, va, acc, out, w, shift, aligned, xs, y0, rows, i0, nin, out_lane);
-        i0 += CH;
-        if (i0 >= nin) break;
-        load_chunk_u8<R, CH>(in, h, w, aligned, xs, y0, i0 + CH, last, va);
-        process_chunk_u8<R, CH>(wt, vb, acc, out, w, shift, aligned, xs, y0, rows, i0, nin, out_lane);
-        i0 += CH;
-        if (i0 >= nin) break;
-    }
+    if (aligned && x0 + 4 * (kLanes - NB) <= w)
+        rows_u8<R, kFast>(wt, in, out, acc, h, w, shift, xs, y0, rows, out_lane);
+    else if (aligned && w >= 4)
+        rows_u8<R, kEdge>(wt, in, out, acc, h, w, shift, xs, y0, rows, out_lane);
+    else
+        rows_u8<R, kTiny>(wt, in, out, acc, h, w, shift, xs, y0, rows, out_lane);
 }
 
 template <int R>

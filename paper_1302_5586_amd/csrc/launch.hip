@@ -39,9 +39,9 @@ hipError_t launch_u8(int r, const uint8_t *in, const int8_t *filt, uint8_t *out,
 void *batch_kernel_fn(int group, bool exact, int mask) {
     if (group == 1) return exact ? batch_fn<1, 1, 3>() : batch_fn<1, 0, 3>();
     switch (mask) {
+        case 1: return exact ? batch_fn<0, 1, 1>() : batch_fn<0, 0, 1>();
         case 2: return exact ? batch_fn<0, 1, 2>() : batch_fn<0, 0, 2>();
-        case 3: return exact ? batch_fn<0, 1, 3>() : batch_fn<0, 0, 3>();
-        default: return exact ? batch_fn<0, 1, 7>() : batch_fn<0, 0, 7>();
+        default: return exact ? batch_fn<0, 1, 3>() : batch_fn<0, 0, 3>();
     }
 }
 
@@ -59,9 +59,9 @@ hipError_t launch_batch(int group, bool exact, int mask, const BatchImg *imgs, c
 #define PF_LB(G, E, M) launch_batch_g<G, E, M>(imgs, task_img, ntasks, grid, wpg, in, filt, out, s)
     if (group == 1) return exact ? PF_LB(1, 1, 3) : PF_LB(1, 0, 3);
     switch (mask) {
+        case 1: return exact ? PF_LB(0, 1, 1) : PF_LB(0, 0, 1);
         case 2: return exact ? PF_LB(0, 1, 2) : PF_LB(0, 0, 2);
-        case 3: return exact ? PF_LB(0, 1, 3) : PF_LB(0, 0, 3);
-        default: return exact ? PF_LB(0, 1, 7) : PF_LB(0, 0, 7);
+        default: return exact ? PF_LB(0, 1, 3) : PF_LB(0, 0, 3);
     }
 #undef PF_LB
 }

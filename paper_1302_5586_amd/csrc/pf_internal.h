@@ -12,15 +12,16 @@
 namespace pf {
 
 // A wave strip is 64 lanes x 4 columns. halo_lanes: neighbouring lanes on
-// each side whose columns a lane's window needs. For radii 1..4 every lane
-// produces outputs (256 columns, 1 KiB of FP32) and lanes 0 and 63 also
-// load the r columns beyond the strip; for larger radii the outermost
+// each side whose columns a lane's window needs. For radii 1 and 2 every
+// lane produces outputs (256 columns, 1 KiB of FP32) and lanes 0 and 63
+// also load the r columns beyond the strip (r registers per row); for
+// larger radii, where those registers would cost occupancy, the outermost
 // lanes only load halo columns and do not store.
 #ifndef PF_STRIP_ALIGNED
 #define PF_STRIP_ALIGNED 1
 #endif
 constexpr int halo_lanes(int r) { return (r + 3) / 4; }
-constexpr bool aligned_strip(int r) { return PF_STRIP_ALIGNED && r >= 1 && r <= 4; }
+constexpr bool aligned_strip(int r) { return PF_STRIP_ALIGNED && r >= 1 && r <= 2; }
 constexpr int idle_lanes(int r) { return aligned_strip(r) ? 0 : halo_lanes(r); }
 constexpr int strip_width(int r) { return 4 * (64 - 2 * idle_lanes(r)); }
 // The uint8 strip keeps its halo lanes at every radius.
@@ -93,8 +94,10 @@ PF_DECL_RADIUS(8)
 #undef PF_DECL_RADIUS
 
 // Batch kernels per (radius group, exact, variant mask), each in its own
-// unit. Masks: bit v for variant v; group 0 has masks 2 (separable only),
-// 3 (direct + separable) and 7 (all); group 1 has mask 3.
+// unit. Masks: bit v for variant v; group 0 has masks 1 (direct only),
+// 2 (separable only) and 3 (both); group 1 has mask 3. The separable-as-2D
+// variant is not compiled into batch kernels (it runs in single-image calls
+// only) so that the persistent kernel stays small.
 template <int G, int E, int M>
 void *batch_fn();
 template <int G, int E, int M>
@@ -106,12 +109,12 @@ hipError_t launch_batch_g(const BatchImg *imgs, const int32_t *task_img, int nta
     template <>                                                                                                \
     hipError_t launch_batch_g<G, E, M>(const BatchImg *imgs, const int32_t *task_img, int ntasks, int grid,     \
                                        int wpg, const float *in, const float *filt, float *out, hipStream_t s);
+PF_DECL_BATCH(0, 0, 1)
+PF_DECL_BATCH(0, 1, 1)
 PF_DECL_BATCH(0, 0, 2)
 PF_DECL_BATCH(0, 1, 2)
 PF_DECL_BATCH(0, 0, 3)
 PF_DECL_BATCH(0, 1, 3)
-PF_DECL_BATCH(0, 0, 7)
-PF_DECL_BATCH(0, 1, 7)
 PF_DECL_BATCH(1, 0, 3)
 PF_DECL_BATCH(1, 1, 3)
 #undef PF_DECL_BATCH
@@ -120,9 +123,9 @@ PF_DECL_BATCH(1, 1, 3)
 // if some image runs variant v).
 inline int batch_mask(int group, int used) {
     if (group == 1) return 3;
+    if ((used & ~1) == 0) return 1;
     if ((used & ~2) == 0) return 2;
-    if ((used & ~3) == 0) return 3;
-    return 7;
+    return 3;
 }
 
 // Tune table lookup (tune.cpp).

@@ -55,9 +55,10 @@ bool entry_ok(const pf_tune_entry &e) {
     if (e.kind < 0 || e.kind >= kKinds || e.r < 0 || e.r > PF_R_MAX || e.size_class < 0 || e.size_class >= kSizes)
         return false;
     if (!valid_shape(e.rows_per_wave, e.waves_per_group)) return false;
-    // The 2D form of a separable filter holds (2r+1)^2 product weights in
-    // registers; it is offered only up to r = 2.
-    if (e.kind == PF_KIND_SEP) return e.variant == PF_VAR_SEPARABLE || (e.variant == PF_VAR_SEP_DIRECT && e.r <= 2);
+    // A separable filter runs separable: the persistent batch kernel
+    // compiles only the direct and separable bodies, and the table must give
+    // single-image calls and batches the same variant for the same key.
+    if (e.kind == PF_KIND_SEP) return e.variant == PF_VAR_SEPARABLE;
     return e.variant == PF_VAR_DIRECT;
 }
 
@@ -274,7 +275,7 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
                 for (int r = 0; r <= r_max && st == PF_OK; ++r) {
                     pf_tune_entry best = default_entry(kind, r, sc);
                     best.us = INFINITY;
-                    const int nvars = kind == PF_KIND_SEP ? (r <= 2 ? 2 : 1) : 1;
+                    const int nvars = 1;
                     for (int vi = 0; vi < nvars && st == PF_OK; ++vi) {
                         const int var = kind == PF_KIND_SEP ? (vi == 0 ? PF_VAR_SEPARABLE : PF_VAR_SEP_DIRECT) : PF_VAR_DIRECT;
                         for (int by : bys)
