@@ -49,10 +49,36 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--tune", default=os.path.join(ROOT, "paper_1302_5586_amd", "tune_mi355x.json"))
+    ap.add_argument("--autotune", default="",
+                    help="tune the table (per class, then on the batch workload), write it to this path, and "
+                         "bench with it")
     ap.add_argument("--skip", default="", help="comma list of sections to skip: plain,large,rgb,serve,cpu")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 512 MiB device copy 4 times (reference for counter scaling)")
     return ap.parse_args()
+
+
+KERNEL_SOURCES = ("paper_1302_5586_amd/csrc/filter_body.h", "paper_1302_5586_amd/csrc/pf_internal.h",
+                  "paper_1302_5586_amd/csrc/batch_inst.hip", "paper_1302_5586_amd/csrc/f32_inst.hip",
+                  "paper_1302_5586_amd/csrc/launch.hip")
+
+
+def committed_traffic(tag):
+    """HBM bytes per launch of a kernel from the committed counter profile
+    (profiles/counters.json), or None when the kernel sources changed since
+    the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    doc = json.load(open(path))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if doc.get("source_hash") != h.hexdigest()[:16]:
+        return None
+    k = doc.get("kernels", {}).get(tag)
+    return None if k is None else k.get("traffic_bytes")
 
 
 def time_events(torch, fn, reps, stream):
@@ -85,9 +111,15 @@ def main():
     torch.cuda.set_device(dev)
     pf.load()
     stream = torch.cuda.current_stream()
-    if os.path.exists(args.tune):
+    if args.autotune:
+        t0 = time.time()
+        pf.autotune(r_max=4, reps=20)
+        log("class autotune done (%.1f s)" % (time.time() - t0))
+    elif os.path.exists(args.tune):
         pf.tune_load(args.tune)
         log("tune table: %s" % args.tune)
+    else:
+        log("tune table: built-in defaults")
 
     if args.calibrate_copy:
         # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
@@ -110,6 +142,11 @@ def main():
     x = torch.from_numpy(pk.pixels).to(dev)
     fl = torch.from_numpy(pk.filters).to(dev)
     out = torch.empty_like(x)
+    if args.autotune:
+        t0 = time.time()
+        pf.autotune_batch(pk.h, pk.w, pk.r, pk.kind, pk.pix_off, pk.filt_off, x, fl, out, reps=10,
+                          path=args.autotune)
+        log("batch autotune done, table written to %s (%.1f s)" % (args.autotune, time.time() - t0))
     plan = pf.BatchPlan(pk.h, pk.w, pk.r, pk.kind, pk.pix_off, pk.filt_off, x.numel(), fl.numel(), graph=True)
     info = plan.info()
     variants = plan.variants()
@@ -155,7 +192,8 @@ def main():
                    "variants": {name: int((variants == v).sum()) for v, name in
                                 ((0, "direct"), (1, "separable"), (2, "separable_as_2d"))}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_traffic("k_batch_f32_batch512"),
+                     "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_batch_f32", "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_kernel_ms": round(k_avg_ms, 4)},
     }

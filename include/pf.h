@@ -169,6 +169,19 @@ pf_status pf_tune_save(const char *path);
  * table to `path` if it is not NULL. Allocates and frees its own device
  * buffers; synchronises the device. */
 pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path);
+/* Tune the table for one batch (the arguments of pf_batch_plan_create and
+ * pf_batch_plan_run): for each size class present in the batch, try row
+ * tiles of 8, 16, 32 and 64 for every radius and FP32 kind of that class,
+ * timing whole-batch launches on the device (median of 5 x `reps`), and
+ * keep a change only when the batch gets at least 3% faster. Installs the
+ * result and writes it to `path` if not NULL. Overwrites `out`. */
+pf_status pf_batch_autotune(int32_t n,
+                            PF_ARR(const int32_t, h, n), PF_ARR(const int32_t, w, n),
+                            PF_ARR(const int32_t, r, n), PF_ARR(const int32_t, kind, n),
+                            PF_ARR(const int64_t, pix_off, n), PF_ARR(const int64_t, filt_off, n),
+                            int64_t npix, int64_t nfilt,
+                            PF_ARR(const float, in, npix), PF_ARR(const float, filt, nfilt),
+                            PF_ARR(float, out, npix), int32_t reps, const char *path);
 
 /* ---- batch: many images, one persistent launch ---------------------------
  * n images described by host arrays (sizes first): image i has h[i] x w[i]

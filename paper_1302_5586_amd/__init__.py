@@ -100,6 +100,7 @@ _SIGS = {
     "pf_tune_load": (_I32, [ctypes.c_char_p]),
     "pf_tune_save": (_I32, [ctypes.c_char_p]),
     "pf_autotune": (_I32, [_I32, _I32, ctypes.c_char_p]),
+    "pf_batch_autotune": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _I64, _I64, _P, _P, _P, _I32, ctypes.c_char_p]),
     "pf_batch_plan_create": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _I64, _I64, _I32, ctypes.POINTER(_P)]),
     "pf_batch_plan_run": (_I32, [_P, _I64, _I64, _P, _P, _P, _P]),
     "pf_batch_plan_variants": (_I32, [_P, _I32, _P]),
@@ -293,6 +294,19 @@ def autotune(r_max: int = 4, reps: int = 20, path: str | None = None):
     """Time every candidate variant and launch shape on the current GPU and
     install the fastest per (kind, radius, size class)."""
     _check(load().pf_autotune(r_max, reps, path.encode() if path else None))
+
+
+def autotune_batch(h, w, r, kind, pix_off, filt_off, x, filt, out, reps: int = 10, path: str | None = None):
+    """Tune the tile heights of the table on one batch (see pf_batch_autotune)."""
+    torch = _torch()
+    _dev_tensor(x, torch.float32, "x")
+    _dev_tensor(filt, torch.float32, "filt")
+    _dev_tensor(out, torch.float32, "out")
+    hh, ww, rr, kk = _i32(h), _i32(w), _i32(r), _i32(kind)
+    po, fo = _i64(pix_off), _i64(filt_off)
+    _check(load().pf_batch_autotune(hh.size, _np_ptr(hh), _np_ptr(ww), _np_ptr(rr), _np_ptr(kk), _np_ptr(po),
+                                    _np_ptr(fo), x.numel(), filt.numel(), x.data_ptr(), filt.data_ptr(),
+                                    out.data_ptr(), reps, path.encode() if path else None))
 
 
 # ---------------------------------------------------------------- batches

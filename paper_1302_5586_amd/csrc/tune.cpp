@@ -34,8 +34,10 @@ pf_tune_entry default_entry(int kind, int r, int sc) {
     e.r = r;
     e.size_class = sc;
     e.variant = (kind == PF_KIND_SEP) ? PF_VAR_SEPARABLE : PF_VAR_DIRECT;
-    e.rows_per_wave = sc == 0 ? 8 : (sc == 1 ? 16 : 32);
-    e.waves_per_group = 4;
+    // Defaults measured on MI355X: 16-row tiles for small images (and for
+    // the uint8 path), 32-row tiles otherwise.
+    e.rows_per_wave = (sc == 0 || kind == PF_KIND_U8) ? 16 : 32;
+    e.waves_per_group = kind == PF_KIND_U8 ? 1 : 4;
     e.us = 0.0f;
     return e;
 }
@@ -128,12 +130,71 @@ pf_status time_launch(F &&launch, int nbuf, int reps, int trials, hipStream_t s,
     return PF_OK;
 }
 
-// Representative image of each size class.
-void class_shape(int sc, int *h, int *w) {
-    static const int hs[kSizes] = {160, 600, 2048};
-    static const int ws[kSizes] = {200, 700, 2048};
+// Representative image of each size class, and how many of them one
+// timed batch holds. Small and medium images are timed the way they run in
+// practice, many at once in the persistent batch kernel; large ones as
+// single launches.
+void class_shape(int sc, int kind, int *h, int *w, int *n) {
+    static const int hs[kSizes] = {160, 600, 4096};
+    static const int ws[kSizes] = {200, 700, 4096};
+    static const int ns[kSizes] = {1024, 96, 1};
     *h = hs[sc];
     *w = ws[sc];
+    *n = ns[sc];
+    if (kind == PF_KIND_U8 && sc == 2) {  // planar RGB at 1080p
+        *h = 1080;
+        *w = 1920;
+    }
+}
+
+// Time one persistent batch launch over n images of h x w with radius r,
+// filter kind `kind` and row tiles of `by`, reading in[] and writing out[]
+// (n*h*w floats each) with the weights at filt.
+pf_status time_batch_class(int kind, int r, int h, int w, int n, int by, const float *in, float *out,
+                           const float *filt, int reps, hipStream_t s, float *us) {
+    const int g = r <= 4 ? 0 : 1;
+    const int var = kind == PF_KIND_SEP ? PF_VAR_SEPARABLE : PF_VAR_DIRECT;
+    const int mask = batch_mask(g, 1 << var);
+    std::vector<BatchImg> imgs(n);
+    std::vector<int32_t> tasks;
+    const int sy = (h + by - 1) / by, sx = (w + strip_width(r) - 1) / strip_width(r);
+    for (int i = 0; i < n; ++i) {
+        BatchImg &d = imgs[i];
+        d.in_off = d.out_off = (int64_t)i * h * w;
+        d.filt_off = 0;
+        d.h = h;
+        d.w = w;
+        d.r = r;
+        d.var = var;
+        d.by = by;
+        d.strips_y = sy;
+        d.task_base = (int32_t)tasks.size();
+        d.pad = 0;
+        tasks.insert(tasks.end(), (size_t)sx * sy, i);
+    }
+    void *dev = nullptr;
+    const size_t bi = imgs.size() * sizeof(BatchImg), bt = tasks.size() * 4;
+    hipError_t e = hipMalloc(&dev, bi + bt);
+    if (e != hipSuccess) return fail_hip(e, "autotune descriptors");
+    e = hipMemcpy(dev, imgs.data(), bi, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((char *)dev + bi, tasks.data(), bt, hipMemcpyHostToDevice);
+    pf_status st = PF_OK;
+    if (e != hipSuccess) {
+        st = fail_hip(e, "autotune descriptors");
+    } else {
+        const int wpg = 4;
+        const int grid = (int)std::min<int64_t>(((int64_t)tasks.size() + wpg - 1) / wpg,
+                                                batch_grid_limit(g, false, mask, wpg));
+        st = time_launch(
+            [&](int) {
+                return launch_batch(g, false, mask, (const BatchImg *)dev, (const int32_t *)((char *)dev + bi),
+                                    (int)tasks.size(), grid, wpg, in, filt, out, s);
+            },
+            1, reps, 5, s, us);
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(dev);
+    return st;
 }
 
 }  // namespace
@@ -257,68 +318,80 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
     if (he != hipSuccess) return fail_hip(he, "stream");
     std::vector<pf_tune_entry> out;
     pf_status st = PF_OK;
+    // One pair of buffers large enough for every class: 4 rotating sets of
+    // 4096 x 4096 floats (512 MiB touched per rotation, more than the 256 MB
+    // last-level cache holds).
+    const size_t big = (size_t)4096 * 4096;
+    const int nrot = 4;
+    float *in = nullptr, *outb = nullptr, *filt = nullptr;
+    if ((he = hipMalloc(&in, big * 4 * nrot)) != hipSuccess || (he = hipMalloc(&outb, big * 4 * nrot)) != hipSuccess ||
+        (he = hipMalloc(&filt, 4096)) != hipSuccess) {
+        st = fail_hip(he, "autotune allocation");
+    } else {
+        (void)hipMemsetAsync(in, 0, big * 4 * nrot, s);
+        (void)hipMemsetAsync(filt, 0, 4096, s);
+    }
     for (int sc = 0; sc < kSizes && st == PF_OK; ++sc) {
-        int h, w;
-        class_shape(sc, &h, &w);
-        const size_t px = (size_t)h * w;
-        // Rotate buffers so that at least 512 MiB is touched per rotation:
-        // the 256 MB last-level cache cannot serve the large class.
-        const int nbuf = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)512 << 20) / (px * 8) + 1));
-        float *in = nullptr, *outb = nullptr, *filt = nullptr;
-        if ((he = hipMalloc(&in, px * 4 * nbuf)) != hipSuccess || (he = hipMalloc(&outb, px * 4 * nbuf)) != hipSuccess ||
-            (he = hipMalloc(&filt, 4096)) != hipSuccess) {
-            st = fail_hip(he, "autotune allocation");
-        } else {
-            (void)hipMemsetAsync(in, 0, px * 4 * nbuf, s);
-            (void)hipMemsetAsync(filt, 0, 4096, s);
-            for (int kind = 0; kind < kKinds && st == PF_OK; ++kind) {
-                for (int r = 0; r <= r_max && st == PF_OK; ++r) {
-                    pf_tune_entry best = default_entry(kind, r, sc);
-                    best.us = INFINITY;
-                    const int nvars = 1;
-                    for (int vi = 0; vi < nvars && st == PF_OK; ++vi) {
-                        const int var = kind == PF_KIND_SEP ? (vi == 0 ? PF_VAR_SEPARABLE : PF_VAR_SEP_DIRECT) : PF_VAR_DIRECT;
-                        for (int by : bys)
-                            for (int wpg : wpgs) {
-                                if (st != PF_OK) break;
-                                float us = 0.0f;
-                                if (kind == PF_KIND_U8) {
-                                    // uint8: 3 planes of the class shape, bytes fit in the same buffers
-                                    const uint8_t *ib = (const uint8_t *)in;
-                                    uint8_t *ob = (uint8_t *)outb;
-                                    const size_t plane3 = 3 * px;
-                                    const int nb8 = (int)std::max<size_t>(1, (px * 4 * nbuf) / plane3);
-                                    st = time_launch(
-                                        [&](int i) {
-                                            return launch_u8(r, ib + (size_t)i * plane3, (const int8_t *)filt,
-                                                             ob + (size_t)i * plane3, 3, h, w, 6, by, wpg, s);
-                                        },
-                                        std::min(nb8, nbuf), reps, 3, s, &us);
-                                } else {
-                                    st = time_launch(
-                                        [&](int i) {
-                                            return launch_f32(r, var, false, in + (size_t)i * px, filt,
-                                                              filt + (2 * r + 1), outb + (size_t)i * px, h, w, by, wpg, s);
-                                        },
-                                        nbuf, reps, 3, s, &us);
-                                }
-                                if (st == PF_OK && us < best.us) {
-                                    best.variant = var;
-                                    best.rows_per_wave = by;
-                                    best.waves_per_group = wpg;
-                                    best.us = us;
-                                }
-                            }
+        for (int kind = 0; kind < kKinds && st == PF_OK; ++kind) {
+            int h, w, n;
+            class_shape(sc, kind, &h, &w, &n);
+            const size_t px = (size_t)h * w;
+            for (int r = 0; r <= r_max && st == PF_OK; ++r) {
+                const pf_tune_entry dflt = default_entry(kind, r, sc);
+                pf_tune_entry best = dflt;
+                best.us = INFINITY;
+                const int var = kind == PF_KIND_SEP ? PF_VAR_SEPARABLE : PF_VAR_DIRECT;
+                // The default shape is timed first; another shape replaces
+                // it only when at least 3% faster, so timing noise does not
+                // move the table.
+                std::vector<std::pair<int, int>> shapes;
+                shapes.push_back({dflt.rows_per_wave, dflt.waves_per_group});
+                for (int by : bys)
+                    for (int wpg : wpgs)
+                        if (by != dflt.rows_per_wave || wpg != dflt.waves_per_group) shapes.push_back({by, wpg});
+                for (const auto &shape : shapes) {
+                    const int by = shape.first, wpg = shape.second;
+                    {
+                        if (st != PF_OK) break;
+                        float us = 0.0f;
+                        if (kind == PF_KIND_U8) {
+                            // uint8: 3 planes of the class shape
+                            const size_t plane3 = 3 * px;
+                            const int nb8 = (int)std::min<size_t>(nrot * 4, (big * 4 * nrot) / plane3);
+                            st = time_launch(
+                                [&](int i) {
+                                    return launch_u8(r, (const uint8_t *)in + (size_t)i * plane3, (const int8_t *)filt,
+                                                     (uint8_t *)outb + (size_t)i * plane3, 3, h, w, 6, by, wpg, s);
+                                },
+                                std::max(nb8, 1), reps, 3, s, &us);
+                        } else if (n > 1) {
+                            // batch kernels use 4 waves per group; time each tile height once
+                            if (wpg != 4 && !(by == dflt.rows_per_wave && wpg == dflt.waves_per_group)) continue;
+                            st = time_batch_class(kind, r, h, w, n, by, in, outb, filt, reps, s, &us);
+                        } else {
+                            st = time_launch(
+                                [&](int i) {
+                                    return launch_f32(r, var, false, in + (size_t)i * px, filt, filt + (2 * r + 1),
+                                                      outb + (size_t)i * px, h, w, by, wpg, s);
+                                },
+                                nrot, reps, 3, s, &us);
+                        }
+                        if (st == PF_OK && (best.us == INFINITY || us < 0.97f * best.us)) {
+                            best.variant = var;
+                            best.rows_per_wave = by;
+                            best.waves_per_group = wpg;
+                            best.us = us;
+                        }
                     }
-                    out.push_back(best);
                 }
+                out.push_back(best);
             }
         }
-        (void)hipStreamSynchronize(s);
-        if (in) (void)hipFree(in);
-        if (outb) (void)hipFree(outb);
-        if (filt) (void)hipFree(filt);
     }
+    (void)hipStreamSynchronize(s);
+    if (in) (void)hipFree(in);
+    if (outb) (void)hipFree(outb);
+    if (filt) (void)hipFree(filt);
     (void)hipStreamDestroy(s);
     if (st != PF_OK) return st;
     // Keys not measured (r > r_max) keep their defaults.
@@ -326,6 +399,65 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
         std::lock_guard<std::mutex> lk(g_mu);
         for (const pf_tune_entry &e : out) g_table.e[e.kind][e.r][e.size_class] = e;
     }
+    if (path) return pf_tune_save(path);
+    return PF_OK;
+}
+
+pf_status pf_batch_autotune(int32_t n, const int32_t *__restrict h, const int32_t *__restrict w,
+                            const int32_t *__restrict r, const int32_t *__restrict kind,
+                            const int64_t *__restrict pix_off, const int64_t *__restrict filt_off, int64_t npix,
+                            int64_t nfilt, const float *in, const float *filt, float *out, int32_t reps,
+                            const char *path) {
+    clear_error();
+    if (reps < 1) return fail(PF_EINVAL, "reps must be >= 1");
+    hipStream_t s = nullptr;
+    hipError_t he = hipStreamCreate(&s);
+    if (he != hipSuccess) return fail_hip(he, "stream");
+    // Median time of `reps` replays of a plan built from the active table.
+    auto measure = [&](float *us) -> pf_status {
+        pf_batch_plan *plan = nullptr;
+        pf_status st = pf_batch_plan_create(n, h, w, r, kind, pix_off, filt_off, npix, nfilt, 0, &plan);
+        if (st) return st;
+        st = time_launch([&](int) -> hipError_t {
+            return pf_batch_plan_run(plan, npix, nfilt, in, filt, out, s) == PF_OK ? hipSuccess : hipErrorLaunchFailure;
+        }, 1, reps, 5, s, us);
+        (void)hipStreamSynchronize(s);
+        pf_batch_plan_destroy(plan);
+        return st;
+    };
+    bool present[kSizes] = {false, false, false};
+    for (int i = 0; i < n; ++i) present[size_class((int64_t)h[i] * w[i])] = true;
+    float best = 0.0f;
+    pf_status st = measure(&best);
+    const int bys[] = {8, 16, 32, 64};
+    // Coordinate descent: one size class at a time, every radius and both
+    // FP32 kinds of that class move together; a new tile height is kept
+    // only when the whole batch gets at least 3% faster.
+    for (int sc = 0; sc < kSizes && st == PF_OK; ++sc) {
+        if (!present[sc]) continue;
+        for (int by : bys) {
+            Table saved;
+            {
+                std::lock_guard<std::mutex> lk(g_mu);
+                saved = g_table;
+                for (int k = 0; k < 2; ++k)
+                    for (int rr = 0; rr <= PF_R_MAX; ++rr) g_table.e[k][rr][sc].rows_per_wave = by;
+            }
+            float us = 0.0f;
+            st = measure(&us);
+            if (st != PF_OK || !(us < 0.97f * best)) {
+                std::lock_guard<std::mutex> lk(g_mu);
+                g_table = saved;
+            } else {
+                best = us;
+                std::lock_guard<std::mutex> lk(g_mu);
+                for (int k = 0; k < 2; ++k)
+                    for (int rr = 0; rr <= PF_R_MAX; ++rr) g_table.e[k][rr][sc].us = us;
+            }
+        }
+    }
+    (void)hipStreamDestroy(s);
+    if (st != PF_OK) return st;
     if (path) return pf_tune_save(path);
     return PF_OK;
 }

@@ -177,3 +177,30 @@ def test_config_batch_512():
             for y, xx in zip(ys, xs):
                 o = float(oracle.filter2d_f32_at(b.images[i], f2, r, int(y), int(xx)))
                 assert abs(float(gi[y, xx]) - o) <= 2e-5 * abs(o) + 1e-30, (i, y, xx)
+
+
+def test_batch_autotune_keeps_results(tmp_path):
+    """Tuning the table on a batch changes only launch shapes: the tuned plan
+    still matches the oracle, and the saved table reloads."""
+    dev = device()
+    import torch
+    imgs, filts, kinds = _mixed_batch(21, 40, hi=700, rmax=4)
+    pk = pf.pack_batch(imgs, filts, kinds)
+    x, fl = _t(pk.pixels, dev), _t(pk.filters, dev)
+    out = torch.zeros_like(x)
+    path = str(tmp_path / "tuned.json")
+    try:
+        pf.autotune_batch(pk.h, pk.w, pk.r, pk.kind, pk.pix_off, pk.filt_off, x, fl, out, reps=2, path=path)
+        pf.tune_reset()
+        pf.tune_load(path)
+        out.zero_()
+        plan = pf.BatchPlan(pk.h, pk.w, pk.r, pk.kind, pk.pix_off, pk.filt_off, x.numel(), fl.numel())
+        plan.run(x, fl, out)
+        got = out.cpu().numpy()
+        for i in range(len(imgs)):
+            h, w, r, k = int(pk.h[i]), int(pk.w[i]), int(pk.r[i]), int(pk.kind[i])
+            gi = got[pk.pix_off[i]:pk.pix_off[i] + h * w].reshape(h, w)
+            ref, tol = _oracle_and_tol(imgs[i], filts[i], k, r)
+            assert_close(gi, ref, tol, "tuned batch image %d (%dx%d r=%d kind=%d)" % (i, h, w, r, k))
+    finally:
+        pf.tune_reset()
