@@ -144,7 +144,7 @@ def main():
     out = torch.empty_like(x)
     if args.autotune:
         t0 = time.time()
-        pf.autotune_batch(pk.h, pk.w, pk.r, pk.kind, pk.pix_off, pk.filt_off, x, fl, out, reps=10,
+        pf.autotune_batch(pk.h, pk.w, pk.r, pk.kind, pk.pix_off, pk.filt_off, x, fl, out, reps=20,
                           path=args.autotune)
         log("batch autotune done, table written to %s (%.1f s)" % (args.autotune, time.time() - t0))
     plan = pf.BatchPlan(pk.h, pk.w, pk.r, pk.kind, pk.pix_off, pk.filt_off, x.numel(), fl.numel(), graph=True)

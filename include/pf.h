@@ -169,11 +169,19 @@ pf_status pf_tune_save(const char *path);
  * table to `path` if it is not NULL. Allocates and frees its own device
  * buffers; synchronises the device. */
 pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path);
+/* Workgroups (of four waves) per compute unit that persistent batch
+ * launches use, a table-wide setting (saved with the table; reset to its
+ * default, 1, by pf_tune_set and pf_tune_reset). `blocks_per_cu` in 1..8
+ * sets it, 0 leaves it; the value before the call goes to `previous` if
+ * not NULL. Fewer than fit at once is deliberate: on MI355X the fewest
+ * tiles in flight ran fastest. Plans created earlier keep their grid. */
+pf_status pf_tune_batch_blocks(int32_t blocks_per_cu, int32_t *previous);
 /* Tune the table for one batch (the arguments of pf_batch_plan_create and
  * pf_batch_plan_run): for each size class present in the batch, try row
  * tiles of 8, 16, 32 and 64 for every radius and FP32 kind of that class,
  * timing whole-batch launches on the device (median of 5 x `reps`), and
- * keep a change only when the batch gets at least 3% faster. Installs the
+ * keep a change only when the batch gets at least 3% faster. Workgroups per
+ * compute unit (1..4, see pf_tune_batch_blocks) are tuned first. Installs the
  * result and writes it to `path` if not NULL. Overwrites `out`. */
 pf_status pf_batch_autotune(int32_t n,
                             PF_ARR(const int32_t, h, n), PF_ARR(const int32_t, w, n),

@@ -100,6 +100,7 @@ _SIGS = {
     "pf_tune_load": (_I32, [ctypes.c_char_p]),
     "pf_tune_save": (_I32, [ctypes.c_char_p]),
     "pf_autotune": (_I32, [_I32, _I32, ctypes.c_char_p]),
+    "pf_tune_batch_blocks": (_I32, [_I32, _P]),
     "pf_batch_autotune": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _I64, _I64, _P, _P, _P, _I32, ctypes.c_char_p]),
     "pf_batch_plan_create": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _I64, _I64, _I32, ctypes.POINTER(_P)]),
     "pf_batch_plan_run": (_I32, [_P, _I64, _I64, _P, _P, _P, _P]),
@@ -294,6 +295,13 @@ def autotune(r_max: int = 4, reps: int = 20, path: str | None = None):
     """Time every candidate variant and launch shape on the current GPU and
     install the fastest per (kind, radius, size class)."""
     _check(load().pf_autotune(r_max, reps, path.encode() if path else None))
+
+
+def tune_batch_blocks(blocks_per_cu: int = 0) -> int:
+    """Set workgroups per compute unit of batch launches (0: leave); returns the previous value."""
+    prev = ctypes.c_int32(0)
+    _check(load().pf_tune_batch_blocks(blocks_per_cu, ctypes.byref(prev)))
+    return prev.value
 
 
 def autotune_batch(h, w, r, kind, pix_off, filt_off, x, filt, out, reps: int = 10, path: str | None = None):

@@ -4,7 +4,7 @@
 // The batch is described the way the paper rewrites OP2's kernel for
 // PENCIL (Sec. III-A): no arrays of pointers, only arenas plus per-image
 // offsets. Every image's outputs are independent iterations (Sec. II-B.3),
-// so all images' wave tiles form one flat task list that a fixed grid of
+// so all images' wave tiles form one flat list that a fixed grid of
 // workgroups walks with a static stride.
 #include <string.h>
 
@@ -26,9 +26,9 @@ struct pf_batch_plan {
     int32_t grid[2] = {0, 0};
     int32_t mask[2] = {3, 3};  // compiled variant set of each group's kernel
     int32_t wpg = 4;
-    void *dev = nullptr;  // descriptors and task table, one allocation
+    void *dev = nullptr;  // descriptors and tile lists, one allocation
     const pf::BatchImg *imgs[2] = {nullptr, nullptr};
-    const int32_t *task_img[2] = {nullptr, nullptr};
+    const pf::BatchTask *tasks[2] = {nullptr, nullptr};
     // Graph replay state.
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -43,7 +43,7 @@ namespace pf {
 // Sets kernel parameters for group g of plan p (pointers must outlive use).
 struct BatchArgs {
     const BatchImg *imgs;
-    const int32_t *task_img;
+    const BatchTask *tasks;
     int ntasks;
     const float *in;
     const float *filt;
@@ -51,7 +51,7 @@ struct BatchArgs {
     void *params[6];
     void fill() {
         params[0] = &imgs;
-        params[1] = &task_img;
+        params[1] = &tasks;
         params[2] = &ntasks;
         params[3] = &in;
         params[4] = &filt;
@@ -120,7 +120,7 @@ pf_status pf_batch_plan_create(int32_t n, const int32_t *__restrict h, const int
     p->variant.resize(n);
 
     std::vector<BatchImg> imgs[2];
-    std::vector<int32_t> tasks[2];
+    int64_t ntiles[2] = {0, 0};
     int used[2] = {0, 0};
     for (int i = 0; i < n; ++i) {
         const int64_t px = (int64_t)h[i] * w[i];
@@ -144,29 +144,29 @@ pf_status pf_batch_plan_create(int32_t n, const int32_t *__restrict h, const int
         d.r = r[i];
         d.var = var;
         d.by = e.rows_per_wave;
-        d.strips_y = (h[i] + d.by - 1) / d.by;
-        const int64_t sx = (w[i] + strip_width(r[i]) - 1) / strip_width(r[i]);
-        const int64_t nt = sx * d.strips_y;
-        if ((int64_t)tasks[g].size() + nt > INT32_MAX) {
+        const int64_t nt = set_strips(d);
+        if (ntiles[g] + nt > INT32_MAX) {
             delete p;
             return fail(PF_EUNSUPPORTED, "batch has more than 2^31-1 wave tiles");
         }
-        d.task_base = (int32_t)tasks[g].size();
-        d.pad = 0;
-        const int32_t idx = (int32_t)imgs[g].size();
+        ntiles[g] += nt;
         imgs[g].push_back(d);
-        tasks[g].insert(tasks[g].end(), (size_t)nt, idx);
     }
+    std::vector<BatchTask> tasks[2];
     size_t bytes = 0;
     size_t off_imgs[2], off_tasks[2];
     for (int g = 0; g < 2; ++g) {
+        p->ntasks[g] = ntiles[g];
+        p->mask[g] = batch_mask(g, used[g]);
+        p->grid[g] = ntiles[g] ? batch_grid(g, (flags & PF_FLAG_EXACT) != 0, p->mask[g], p->wpg, ntiles[g]) : 0;
+        tasks[g].reserve((size_t)ntiles[g]);
+        for (size_t i = 0; i < imgs[g].size(); ++i) append_tiles(tasks[g], (int32_t)i, imgs[g][i]);
         off_imgs[g] = bytes;
         bytes += imgs[g].size() * sizeof(BatchImg);
         bytes = (bytes + 255) & ~(size_t)255;
         off_tasks[g] = bytes;
-        bytes += tasks[g].size() * sizeof(int32_t);
+        bytes += tasks[g].size() * sizeof(BatchTask);
         bytes = (bytes + 255) & ~(size_t)255;
-        p->ntasks[g] = (int64_t)tasks[g].size();
     }
     hipError_t e = hipMalloc(&p->dev, std::max<size_t>(bytes, 256));
     if (e != hipSuccess) {
@@ -176,13 +176,9 @@ pf_status pf_batch_plan_create(int32_t n, const int32_t *__restrict h, const int
     std::vector<char> host(std::max<size_t>(bytes, 256), 0);
     for (int g = 0; g < 2; ++g) {
         if (!imgs[g].empty()) memcpy(host.data() + off_imgs[g], imgs[g].data(), imgs[g].size() * sizeof(BatchImg));
-        if (!tasks[g].empty()) memcpy(host.data() + off_tasks[g], tasks[g].data(), tasks[g].size() * sizeof(int32_t));
+        if (!tasks[g].empty()) memcpy(host.data() + off_tasks[g], tasks[g].data(), tasks[g].size() * sizeof(BatchTask));
         p->imgs[g] = (const BatchImg *)((char *)p->dev + off_imgs[g]);
-        p->task_img[g] = (const int32_t *)((char *)p->dev + off_tasks[g]);
-        p->mask[g] = batch_mask(g, used[g]);
-        const int64_t need = (p->ntasks[g] + p->wpg - 1) / p->wpg;
-        const int limit = batch_grid_limit(g, (flags & PF_FLAG_EXACT) != 0, p->mask[g], p->wpg);
-        p->grid[g] = p->ntasks[g] ? (int32_t)std::min<int64_t>(need, limit) : 0;
+        p->tasks[g] = (const BatchTask *)((char *)p->dev + off_tasks[g]);
     }
     e = hipMemcpy(p->dev, host.data(), host.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -211,7 +207,7 @@ pf_status pf_batch_plan_run(pf_batch_plan *p, int64_t npix, int64_t nfilt, const
     if (!(p->flags & PF_BATCH_GRAPH)) {
         for (int g = 0; g < 2; ++g) {
             if (!p->ntasks[g]) continue;
-            hipError_t e = launch_batch(g, exact, p->mask[g], p->imgs[g], p->task_img[g], (int)p->ntasks[g], p->grid[g],
+            hipError_t e = launch_batch(g, exact, p->mask[g], p->imgs[g], p->tasks[g], (int)p->ntasks[g], p->grid[g],
                                         p->wpg, in, filt, out, s);
             if (e != hipSuccess) return fail_hip(e, "batch launch");
         }
@@ -224,7 +220,7 @@ pf_status pf_batch_plan_run(pf_batch_plan *p, int64_t npix, int64_t nfilt, const
         hipGraphNode_t prev = nullptr;
         for (int g = 0; g < 2; ++g) {
             if (!p->ntasks[g]) continue;
-            BatchArgs a{p->imgs[g], p->task_img[g], (int)p->ntasks[g], in, filt, out, {}};
+            BatchArgs a{p->imgs[g], p->tasks[g], (int)p->ntasks[g], in, filt, out, {}};
             hipKernelNodeParams kp = node_params(p, g, a);
             e = hipGraphAddKernelNode(&p->node[g], p->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
             if (e != hipSuccess) return fail_hip(e, "graph kernel node");
@@ -241,7 +237,7 @@ pf_status pf_batch_plan_run(pf_batch_plan *p, int64_t npix, int64_t nfilt, const
         // Re-point the replay at the new arenas.
         for (int g = 0; g < 2; ++g) {
             if (!p->ntasks[g]) continue;
-            BatchArgs a{p->imgs[g], p->task_img[g], (int)p->ntasks[g], in, filt, out, {}};
+            BatchArgs a{p->imgs[g], p->tasks[g], (int)p->ntasks[g], in, filt, out, {}};
             hipKernelNodeParams kp = node_params(p, g, a);
             if ((e = hipGraphExecKernelNodeSetParams(p->exec, p->node[g], &kp)) != hipSuccess)
                 return fail_hip(e, "graph node update");

@@ -22,11 +22,11 @@ void *batch_fn<PF_GROUP, PF_EXACT, PF_VMASK>() {
 }
 
 template <>
-hipError_t launch_batch_g<PF_GROUP, PF_EXACT, PF_VMASK>(const BatchImg *imgs, const int32_t *task_img, int ntasks,
+hipError_t launch_batch_g<PF_GROUP, PF_EXACT, PF_VMASK>(const BatchImg *imgs, const BatchTask *tasks, int ntasks,
                                                         int grid, int wpg, const float *in, const float *filt,
                                                         float *out, hipStream_t s) {
     hipLaunchKernelGGL((dev::k_batch_f32<kLo, kHi, kExact, PF_VMASK>), dim3(grid), dim3(wpg * dev::kLanes), 0, s, imgs,
-                       task_img, ntasks, in, filt, out);
+                       tasks, ntasks, in, filt, out);
     return hipGetLastError();
 }
 

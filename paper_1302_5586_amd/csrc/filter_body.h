@@ -51,6 +51,30 @@ constexpr int kLanes = 64;
 // dropped on store and return 0 on load.
 constexpr int kBufferFlags = 0x00020000;
 
+// Outputs are written once and not read back by the kernel: stores carry
+// the non-temporal hint (nt), which streams them to HBM without holding
+// lines in L2 that the inputs' halo rows could use. PF_NT_LOAD puts the
+// same hint on the input loads (off by default: halo rows are read twice).
+#ifndef PF_NT_STORE
+#define PF_NT_STORE 1
+#endif
+#ifndef PF_NT_LOAD
+#define PF_NT_LOAD 0
+#endif
+constexpr int kStoreAux = PF_NT_STORE ? 2 : 0;  // cache-policy operand of buffer stores: nt
+
+template <class T>
+__device__ __forceinline__ T ld(const T *p) {
+    if constexpr (PF_NT_LOAD) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <class T>
+__device__ __forceinline__ void st(T *p, T v) {
+    if constexpr (PF_NT_STORE) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -106,35 +130,6 @@ __device__ __forceinline__ float madd(float wgt, float x, float acc) {
     }
 }
 
-// Four consecutive elements of a row from column xs, clamped to [0, w-1].
-// The fast path is one dwordx4 load; rows need only 4-byte alignment.
-__device__ __forceinline__ void load4(const float *__restrict__ row, int xs, int w, float v[4]) {
-    if (xs >= 0 && xs + 3 < w) {
-        const f4u q = *reinterpret_cast<const f4u *>(row + xs);
-        v[0] = q.x;
-        v[1] = q.y;
-        v[2] = q.z;
-        v[3] = q.w;
-    } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = row[clampi(xs + k, 0, w - 1)];
-    }
-}
-
-__device__ __forceinline__ void store4(float *__restrict__ row, int xs, int w, const float v[4]) {
-    if (xs + 3 < w) {
-        f4u q;
-        q.x = v[0];
-        q.y = v[1];
-        q.z = v[2];
-        q.w = v[3];
-        *reinterpret_cast<f4u *>(row + xs) = q;
-    } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (xs + k < w) row[xs + k] = v[k];
-    }
-}
 
 // ---------------------------------------------------------------- FP32 ---
 
@@ -156,7 +151,7 @@ typedef float f3u __attribute__((ext_vector_type(3), aligned(4)));
 template <int N>
 __device__ __forceinline__ void loadn(const float *__restrict__ p, float (&o)[N]) {
     if constexpr (N == 4) {
-        const f4u q = *reinterpret_cast<const f4u *>(p);
+        const f4u q = ld(reinterpret_cast<const f4u *>(p));
         o[0] = q.x, o[1] = q.y, o[2] = q.z, o[3] = q.w;
     } else if constexpr (N == 3) {
         const f3u q = *reinterpret_cast<const f3u *>(p);
@@ -192,14 +187,14 @@ __device__ __forceinline__ void load_row(const float *__restrict__ row, int xs, 
     if constexpr (MODE == kFast) {
         if constexpr (idle_lanes(R) > 0) {
             // The left halo lane of the first strip sits left of column 0.
-            const f4u t = *reinterpret_cast<const f4u *>(row + max(xs, 0));
+            const f4u t = ld(reinterpret_cast<const f4u *>(row + max(xs, 0)));
             const bool left_of_image = xs < 0;
             q.v[0] = t.x;
             q.v[1] = left_of_image ? t.x : t.y;
             q.v[2] = left_of_image ? t.x : t.z;
             q.v[3] = left_of_image ? t.x : t.w;
         } else {
-            const f4u t = *reinterpret_cast<const f4u *>(row + xs);
+            const f4u t = ld(reinterpret_cast<const f4u *>(row + xs));
             q.v[0] = t.x;
             q.v[1] = t.y;
             q.v[2] = t.z;
@@ -207,7 +202,7 @@ __device__ __forceinline__ void load_row(const float *__restrict__ row, int xs, 
         }
     } else if constexpr (MODE == kEdge) {
         const int xa = clampi(xs, 0, w - 4);
-        const f4u t = *reinterpret_cast<const f4u *>(row + xa);
+        const f4u t = ld(reinterpret_cast<const f4u *>(row + xa));
 #pragma unroll
         for (int k = 0; k < 4; ++k) q.v[k] = pick4(t, clampi(xs + k, 0, w - 1) - xa);
     } else {
@@ -340,14 +335,19 @@ __device__ __forceinline__ void fold_row_f32(const Weights<R, VAR> &wt, const Ro
 }
 
 // Rows per pipelined chunk: a multiple of K (ring residues stay
-// compile-time constants) near PF_CHUNK rows.
+// compile-time constants) near CHUNK rows. Single-image launches run many
+// waves per SIMD and take 8; the persistent batch kernel runs two and
+// hides latency with 12 (both measured on MI355X).
 #ifndef PF_CHUNK
 #define PF_CHUNK 8
 #endif
-template <int R>
+#ifndef PF_BATCH_CHUNK
+#define PF_BATCH_CHUNK 12
+#endif
+template <int R, int CHUNK>
 constexpr int chunk_rows() {
     constexpr int K = 2 * R + 1;
-    return K * (PF_CHUNK / K > 0 ? PF_CHUNK / K : 1);
+    return K * (CHUNK / K > 0 ? CHUNK / K : 1);
 }
 
 // Load input rows [i0, i0 + CH) of a strip. Rows past the strip's last
@@ -380,7 +380,7 @@ __device__ __forceinline__ void store_row(float *__restrict__ out, int w, int xs
         t.y = a[1];
         t.z = a[2];
         t.w = a[3];
-        *reinterpret_cast<f4u *>(o + xs) = t;
+        st(reinterpret_cast<f4u *>(o + xs), t);
     } else if constexpr (MODE == kFast) {
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(o, 0, w * 4, kBufferFlags);
         typedef unsigned u4 __attribute__((ext_vector_type(4)));
@@ -389,13 +389,13 @@ __device__ __forceinline__ void store_row(float *__restrict__ out, int w, int xs
         t.y = __float_as_uint(a[1]);
         t.z = __float_as_uint(a[2]);
         t.w = __float_as_uint(a[3]);
-        __builtin_amdgcn_raw_buffer_store_b128(t, rs, out_lane ? xs * 4 : 0x7ffffff0, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(t, rs, out_lane ? xs * 4 : 0x7ffffff0, 0, kStoreAux);
     } else {
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(o, 0, w * 4, kBufferFlags);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int off = out_lane ? (xs + k) * 4 : 0x7ffffff0;
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(a[k]), rs, off, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(a[k]), rs, off, 0, kStoreAux);
         }
     }
 }
@@ -449,12 +449,12 @@ __device__ __forceinline__ void rows_group_f32(const Weights<R, VAR> &wt, const 
 // of CH rows in two alternating register sets (the loads of one chunk are
 // in flight while the other is folded; no per-row branch inside the loop),
 // then the remaining rows in groups of K.
-template <int R, int VAR, bool EXACT, int MODE>
+template <int R, int VAR, bool EXACT, int MODE, int CHUNK>
 __device__ __forceinline__ void rows_pipelined_f32(const Weights<R, VAR> &wt, const float *__restrict__ in,
                                                    float *__restrict__ out, float (&acc)[2 * R + 1][4], int h, int w,
                                                    int xs, int x0, int lane, int y0, int rows, bool out_lane) {
     constexpr int K = 2 * R + 1;
-    constexpr int CH = chunk_rows<R>();
+    constexpr int CH = chunk_rows<R, CHUNK>();
     const int nin = rows + 2 * R;
     int i0 = 2 * R;
     if (i0 + CH <= nin) {
@@ -497,7 +497,7 @@ __device__ __forceinline__ void rows_pipelined_f32(const Weights<R, VAR> &wt, co
 
 // One wave computes output rows [y0, y0 + rows) of columns [x0, x0 + strip
 // width) of one image plane.
-template <int R, int VAR, bool EXACT>
+template <int R, int VAR, bool EXACT, int CHUNK = PF_CHUNK>
 __device__ __forceinline__ void strip_f32(const float *__restrict__ in, const float *__restrict__ fa,
                                           const float *__restrict__ fb, float *__restrict__ out, int h, int w,
                                           int x0, int y0, int rows, int lane) {
@@ -520,9 +520,9 @@ __device__ __forceinline__ void strip_f32(const float *__restrict__ in, const fl
             rows_group_f32<R, VAR, EXACT, 0, kTiny>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, i0, nin, out_lane);
     } else {
         if (fast_strip<R>(x0, w)) {
-            rows_pipelined_f32<R, VAR, EXACT, kFast>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, out_lane);
+            rows_pipelined_f32<R, VAR, EXACT, kFast, CHUNK>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, out_lane);
         } else if (w >= 4) {
-            rows_pipelined_f32<R, VAR, EXACT, kEdge>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, out_lane);
+            rows_pipelined_f32<R, VAR, EXACT, kEdge, CHUNK>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, out_lane);
         } else {
             const int nin = rows + 2 * R;
             for (int i0 = 0; i0 < nin; i0 += K)
@@ -532,30 +532,53 @@ __device__ __forceinline__ void strip_f32(const float *__restrict__ in, const fl
     }
 }
 
-// Single-image kernel: one wave tile per task, tasks column-major over
-// (strip x, strip y) so the waves of a workgroup are vertically adjacent.
+// Tile number -> (strip x, strip y). Tiles are numbered row-major, so the
+// waves in flight at any moment cover whole bands of consecutive image
+// rows: a compact, slowly advancing window of HBM pages (and of address
+// translations), which MI355X serves markedly faster than the same tiles
+// taken strip by strip down the image.
+// The uint8 kernel keeps column-major order (strip by strip), which
+// measured faster for it.
+#ifndef PF_TILE_COLMAJOR
+#define PF_TILE_COLMAJOR 0
+#endif
+#ifndef PF_U8_COLMAJOR
+#define PF_U8_COLMAJOR 1
+#endif
+template <bool COLMAJOR = PF_TILE_COLMAJOR != 0>
+__device__ __forceinline__ void tile_xy(int t, int strips_x, int strips_y, int &sx, int &sy) {
+    if constexpr (COLMAJOR) {
+        sx = t / strips_y;
+        sy = t - sx * strips_y;
+    } else {
+        sy = t / strips_x;
+        sx = t - sy * strips_x;
+    }
+}
+
+// Single-image kernel: one wave tile per task.
 template <int R, int VAR, bool EXACT>
 __global__ __launch_bounds__(512) void k_filter_f32(const float *__restrict__ in, const float *__restrict__ fa,
                                                     const float *__restrict__ fb, float *__restrict__ out, int h,
-                                                    int w, int by,
-                                                    int strips_y, int ntasks) {
+                                                    int w, int by, int strips_x, int strips_y, int ntasks) {
     const int wpg = blockDim.x / kLanes;
     const int wave = uniform(threadIdx.x / kLanes);
     const int lane = threadIdx.x % kLanes;
     const int t = xcd_remap(blockIdx.x, gridDim.x) * wpg + wave;
     if (t >= ntasks) return;
-    const int sx = t / strips_y, sy = t - sx * strips_y;
+    int sx, sy;
+    tile_xy(t, strips_x, strips_y, sx, sy);
     const int y0 = sy * by;
     strip_f32<R, VAR, EXACT>(in, fa, fb, out, h, w, sx * strip_width(R), y0, min(by, h - y0), lane);
 }
 
-// Persistent batch kernel: a fixed grid of workgroups walks the flattened
-// wave-tile list of all images with a static stride. task_img[t] names the
-// image of task t; the image descriptor gives its radius, variant, tile
-// height and arena offsets.
+// Persistent batch kernel: a fixed grid of workgroups walks the list of all
+// images' wave tiles with a static stride (tiles in image order, row-major
+// inside each image). Each entry names an image and a tile; the image
+// descriptor gives the radius, variant, tile height and arena offsets.
 template <int RLO, int RHI, bool EXACT, int VMASK>
 __global__ __launch_bounds__(512) void k_batch_f32(const BatchImg *__restrict__ imgs,
-                                                   const int32_t *__restrict__ task_img, int ntasks,
+                                                   const BatchTask *__restrict__ tasks, int ntasks,
                                                    const float *__restrict__ in, const float *__restrict__ filt,
                                                    float *__restrict__ out) {
     const int wpg = blockDim.x / kLanes;
@@ -563,10 +586,10 @@ __global__ __launch_bounds__(512) void k_batch_f32(const BatchImg *__restrict__ 
     const int lane = threadIdx.x % kLanes;
     const int stride = gridDim.x * wpg;
     for (int t = xcd_remap(blockIdx.x, gridDim.x) * wpg + wave; t < ntasks; t += stride) {
-        const int i = uniform(task_img[t]);
-        const BatchImg d = imgs[i];
-        const int local = t - d.task_base;
-        const int sx = local / d.strips_y, sy = local - sx * d.strips_y;
+        const BatchTask tk = tasks[t];
+        const BatchImg d = imgs[uniform(tk.img)];
+        int sx, sy;
+        tile_xy(uniform(tk.tile), d.strips_x, d.strips_y, sx, sy);
         const int y0 = sy * d.by;
         const int rows = min(d.by, d.h - y0);
         const float *src = reinterpret_cast<const float *>(reinterpret_cast<uintptr_t>(in) + (uint64_t)d.in_off * 4u);
@@ -582,7 +605,8 @@ __global__ __launch_bounds__(512) void k_batch_f32(const BatchImg *__restrict__ 
                     constexpr int VV = decltype(vc)::value;
                     if constexpr ((VMASK >> VV) & 1) {
                         if (d.var == VV)
-                            strip_f32<RR, VV, EXACT>(src, fa, fb, dst, d.h, d.w, sx * strip_width(RR), y0, rows, lane);
+                            strip_f32<RR, VV, EXACT, PF_BATCH_CHUNK>(src, fa, fb, dst, d.h, d.w, sx * strip_width(RR), y0,
+                                                            rows, lane);
                     }
                 });
             }
@@ -633,11 +657,11 @@ struct WeightsU8 {
 template <int MODE>
 __device__ __forceinline__ uint32_t load_u8(const uint8_t *__restrict__ row, int xs, int w) {
     if constexpr (MODE == kFast) {
-        const uint32_t t = *reinterpret_cast<const uint32_t *>(row + max(xs, 0));
+        const uint32_t t = ld(reinterpret_cast<const uint32_t *>(row + max(xs, 0)));
         return xs < 0 ? (t & 0xffu) * 0x01010101u : t;
     } else if constexpr (MODE == kEdge) {
         const int xa = clampi(xs, 0, w - 4);
-        const uint32_t t = *reinterpret_cast<const uint32_t *>(row + xa);
+        const uint32_t t = ld(reinterpret_cast<const uint32_t *>(row + xa));
         uint32_t v = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) v |= ((t >> (8 * (clampi(xs + k, 0, w - 1) - xa))) & 0xffu) << (8 * k);
@@ -713,11 +737,11 @@ __device__ __forceinline__ void store_u8(uint8_t *__restrict__ row, int xs, int 
     }
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(row, 0, w, kBufferFlags);
     if constexpr (MODE == kFast) {
-        __builtin_amdgcn_raw_buffer_store_b32(pk, rs, out_lane ? xs : 0x7ffffff0, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(pk, rs, out_lane ? xs : 0x7ffffff0, 0, kStoreAux);
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(pk >> (8 * k)), rs, out_lane ? xs + k : 0x7ffffff0, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(pk >> (8 * k)), rs, out_lane ? xs + k : 0x7ffffff0, 0, kStoreAux);
     }
 }
 
@@ -838,7 +862,8 @@ __device__ __forceinline__ void strip_u8(const uint8_t *__restrict__ in, const i
 template <int R>
 __global__ __launch_bounds__(512) void k_filter_u8(const uint8_t *__restrict__ in, const int8_t *__restrict__ filt,
                                                    uint8_t *__restrict__ out, int h, int w, int shift, int aligned,
-                                                   int by, int strips_y, int tasks_per_plane, int ntasks) {
+                                                   int by, int strips_x, int strips_y, int tasks_per_plane,
+                                                   int ntasks) {
     const int wpg = blockDim.x / kLanes;
     const int wave = uniform(threadIdx.x / kLanes);
     const int lane = threadIdx.x % kLanes;
@@ -846,7 +871,8 @@ __global__ __launch_bounds__(512) void k_filter_u8(const uint8_t *__restrict__ i
     if (t >= ntasks) return;
     const int p = t / tasks_per_plane;
     const int local = t - p * tasks_per_plane;
-    const int sx = local / strips_y, sy = local - sx * strips_y;
+    int sx, sy;
+    tile_xy<PF_U8_COLMAJOR != 0>(local, strips_x, strips_y, sx, sy);
     const int y0 = sy * by;
     const int64_t plane = (int64_t)p * h * w;
     strip_u8<R>(in + plane, filt, out + plane, h, w, shift, aligned != 0, sx * strip_width_u8(R), y0,
@@ -873,7 +899,7 @@ hipError_t launch_f32_t(const float *in, const float *fa, const float *fb, float
     const int ntasks = (int)ntasks64;
     const int grid = cdiv(ntasks, wpg);
     hipLaunchKernelGGL((k_filter_f32<R, VAR, EXACT>), dim3(grid), dim3(wpg * kLanes), 0, s, in, fa, fb, out, h, w,
-                       by, strips_y, ntasks);
+                       by, strips_x, strips_y, ntasks);
     return hipGetLastError();
 }
 
@@ -904,7 +930,7 @@ hipError_t launch_u8_t(const uint8_t *in, const int8_t *filt, uint8_t *out, int 
     const int grid = cdiv(ntasks, wpg);
     const int aligned = (w % 4 == 0) && ((uintptr_t)in % 4 == 0) && ((uintptr_t)out % 4 == 0);
     hipLaunchKernelGGL((k_filter_u8<R>), dim3(grid), dim3(wpg * kLanes), 0, s, in, filt, out, h, w, shift, aligned,
-                       by, strips_y, (int)per_plane, ntasks);
+                       by, strips_x, strips_y, (int)per_plane, ntasks);
     return hipGetLastError();
 }
 

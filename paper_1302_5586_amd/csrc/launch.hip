@@ -1,5 +1,7 @@
 // Radius dispatch for the single-image kernels, the uint8 kernels and the
 // batch kernels' entry points.
+#include <algorithm>
+
 #include "filter_body.h"
 
 namespace pf {
@@ -54,9 +56,16 @@ int batch_grid_limit(int group, bool exact, int mask, int wpg) {
     return blocks * dev_info().cus;
 }
 
-hipError_t launch_batch(int group, bool exact, int mask, const BatchImg *imgs, const int32_t *task_img, int ntasks,
+int batch_grid(int group, bool exact, int mask, int wpg, int64_t ntiles) {
+    const int fit = batch_grid_limit(group, exact, mask, wpg);
+    const int64_t want = (int64_t)tune_batch_blocks_per_cu() * dev_info().cus;
+    const int64_t need = (ntiles + wpg - 1) / wpg;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(want, fit), need));
+}
+
+hipError_t launch_batch(int group, bool exact, int mask, const BatchImg *imgs, const BatchTask *tasks, int ntasks,
                         int grid, int wpg, const float *in, const float *filt, float *out, hipStream_t s) {
-#define PF_LB(G, E, M) launch_batch_g<G, E, M>(imgs, task_img, ntasks, grid, wpg, in, filt, out, s)
+#define PF_LB(G, E, M) launch_batch_g<G, E, M>(imgs, tasks, ntasks, grid, wpg, in, filt, out, s)
     if (group == 1) return exact ? PF_LB(1, 1, 3) : PF_LB(1, 0, 3);
     switch (mask) {
         case 1: return exact ? PF_LB(0, 1, 1) : PF_LB(0, 0, 1);

@@ -7,6 +7,8 @@
 
 #include <string>
 
+#include <vector>
+
 #include "pf.h"
 
 namespace pf {
@@ -28,8 +30,8 @@ constexpr int strip_width(int r) { return 4 * (64 - 2 * idle_lanes(r)); }
 constexpr int strip_width_u8(int r) { return 4 * (64 - 2 * halo_lanes(r)); }
 
 // One image of a batch as the persistent kernel sees it. `var` is the
-// executed variant (PF_VAR_*), `by` rows per wave tile, tasks are numbered
-// column-major over (strip x, strip y) inside the image.
+// executed variant (PF_VAR_*), `by` rows per wave tile; the image's wave
+// tiles are numbered column-major over (strip x, strip y).
 // Element offsets are added to the kernel's base pointers as integers, so a
 // descriptor may also carry an absolute address (byte address / 4) with a
 // null base.
@@ -38,8 +40,34 @@ struct BatchImg {
     int64_t out_off;
     int64_t filt_off;
     int32_t h, w, r, var;
-    int32_t by, strips_y, task_base, pad;
+    int32_t by, strips_x, strips_y, pad;
 };
+
+// One entry of a wave's tile list: the image (index into the descriptor
+// array) and the tile's number inside the image.
+struct BatchTask {
+    int32_t img, tile;
+};
+
+// Fills strips_x and strips_y of a descriptor whose r, h, w and by are set;
+// returns its wave-tile count.
+inline int64_t set_strips(BatchImg &d) {
+    d.strips_x = (d.w + strip_width(d.r) - 1) / strip_width(d.r);
+    d.strips_y = (d.h + d.by - 1) / d.by;
+    d.pad = 0;
+    return (int64_t)d.strips_x * d.strips_y;
+}
+
+// Appends the wave tiles of image `img` (descriptor d) to a batch's tile list.
+inline void append_tiles(std::vector<BatchTask> &list, int32_t img, const BatchImg &d) {
+    const int32_t n = d.strips_x * d.strips_y;
+    for (int32_t t = 0; t < n; ++t) list.push_back({img, t});
+}
+
+// Workgroups of a batch launch over `ntiles` wave tiles: `blocks_per_cu`
+// per compute unit (from the tune table), at most what fits at once, at
+// most one tile per wave.
+int batch_grid(int group, bool exact, int mask, int wpg, int64_t ntiles);
 
 // Size class used by the tune table.
 inline int size_class(int64_t pixels) {
@@ -67,9 +95,9 @@ hipError_t launch_u8(int r, const uint8_t *in, const int8_t *filt, uint8_t *out,
                      int w, int shift, int by, int wpg, hipStream_t s);
 // Persistent batch kernel over images with r <= 4 (group 0) or r in 5..8
 // (group 1), compiled with the variants of `mask` (see batch_mask).
-hipError_t launch_batch(int group, bool exact, int mask, const BatchImg *imgs, const int32_t *task_img,
-                        int ntasks, int grid, int wpg, const float *in, const float *filt,
-                        float *out, hipStream_t s);
+hipError_t launch_batch(int group, bool exact, int mask, const BatchImg *imgs, const BatchTask *tasks,
+                        int ntasks, int grid, int wpg, const float *in, const float *filt, float *out,
+                        hipStream_t s);
 // Workgroups of the batch kernel that fit on the device at once.
 int batch_grid_limit(int group, bool exact, int mask, int wpg);
 void *batch_kernel_fn(int group, bool exact, int mask);
@@ -101,13 +129,13 @@ PF_DECL_RADIUS(8)
 template <int G, int E, int M>
 void *batch_fn();
 template <int G, int E, int M>
-hipError_t launch_batch_g(const BatchImg *imgs, const int32_t *task_img, int ntasks, int grid, int wpg,
+hipError_t launch_batch_g(const BatchImg *imgs, const BatchTask *tasks, int ntasks, int grid, int wpg,
                           const float *in, const float *filt, float *out, hipStream_t s);
 #define PF_DECL_BATCH(G, E, M)                                                                                 \
     template <>                                                                                                \
     void *batch_fn<G, E, M>();                                                                                 \
     template <>                                                                                                \
-    hipError_t launch_batch_g<G, E, M>(const BatchImg *imgs, const int32_t *task_img, int ntasks, int grid,     \
+    hipError_t launch_batch_g<G, E, M>(const BatchImg *imgs, const BatchTask *tasks, int ntasks, int grid,      \
                                        int wpg, const float *in, const float *filt, float *out, hipStream_t s);
 PF_DECL_BATCH(0, 0, 1)
 PF_DECL_BATCH(0, 1, 1)
@@ -130,6 +158,8 @@ inline int batch_mask(int group, int used) {
 
 // Tune table lookup (tune.cpp).
 pf_tune_entry tune_lookup(int kind, int r, int64_t pixels);
+// Workgroups per compute unit of persistent batch launches (tune.cpp).
+int tune_batch_blocks_per_cu();
 
 bool valid_shape(int by, int wpg);
 

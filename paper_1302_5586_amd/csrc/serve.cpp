@@ -165,7 +165,7 @@ void release_locked(pf_server *s, const std::shared_ptr<Request> &q) {
 pf_status launch_slot(pf_server *s, Slot &sl) {
     const bool exact = (s->flags & PF_FLAG_EXACT) != 0;
     std::vector<BatchImg> imgs[2];
-    std::vector<int32_t> tasks[2];
+    int64_t ntiles[2] = {0, 0};
     std::vector<float> weights;
     int used[2] = {0, 0};
     for (auto &q : sl.reqs) {
@@ -180,13 +180,19 @@ pf_status launch_slot(pf_server *s, Slot &sl) {
         d.r = q->r;
         d.var = q->var;
         d.by = q->by;
-        d.strips_y = (q->h + d.by - 1) / d.by;
-        const int64_t nt = (int64_t)((q->w + strip_width(q->r) - 1) / strip_width(q->r)) * d.strips_y;
-        d.task_base = (int32_t)tasks[g].size();
-        d.pad = 0;
         used[g] |= 1 << q->var;
-        tasks[g].insert(tasks[g].end(), (size_t)nt, (int32_t)imgs[g].size());
+        ntiles[g] += set_strips(d);
         imgs[g].push_back(d);
+    }
+    const int wpg = 4;
+    int mask[2], grid[2] = {0, 0};
+    std::vector<BatchTask> tasks[2];
+    for (int g = 0; g < 2; ++g) {
+        mask[g] = batch_mask(g, used[g]);
+        if (!ntiles[g]) continue;
+        grid[g] = batch_grid(g, exact, mask[g], wpg, ntiles[g]);
+        tasks[g].reserve((size_t)ntiles[g]);
+        for (size_t i = 0; i < imgs[g].size(); ++i) append_tiles(tasks[g], (int32_t)i, imgs[g][i]);
     }
     // Layout: [weights][imgs0][imgs1][tasks0][tasks1], 256-byte aligned parts.
     auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -197,7 +203,7 @@ pf_status launch_slot(pf_server *s, Slot &sl) {
     }
     for (int g = 0; g < 2; ++g) {
         off_t[g] = bytes;
-        bytes = up(bytes + tasks[g].size() * 4);
+        bytes = up(bytes + tasks[g].size() * sizeof(BatchTask));
     }
     hipError_t e;
     if (bytes > sl.cap) {
@@ -214,7 +220,7 @@ pf_status launch_slot(pf_server *s, Slot &sl) {
     memcpy(h + off_w, weights.data(), weights.size() * 4);
     for (int g = 0; g < 2; ++g) {
         memcpy(h + off_i[g], imgs[g].data(), imgs[g].size() * sizeof(BatchImg));
-        memcpy(h + off_t[g], tasks[g].data(), tasks[g].size() * 4);
+        memcpy(h + off_t[g], tasks[g].data(), tasks[g].size() * sizeof(BatchTask));
     }
     // Upload-mode inputs first, then descriptors, then the kernels.
     for (auto &q : sl.reqs)
@@ -225,14 +231,10 @@ pf_status launch_slot(pf_server *s, Slot &sl) {
         }
     if ((e = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, sl.stream)) != hipSuccess)
         return fail_hip(e, "server descriptor upload");
-    const int wpg = 4;
     for (int g = 0; g < 2; ++g) {
-        if (tasks[g].empty()) continue;
-        const int mask = batch_mask(g, used[g]);
-        const int64_t need = ((int64_t)tasks[g].size() + wpg - 1) / wpg;
-        const int grid = (int)std::min<int64_t>(need, batch_grid_limit(g, exact, mask, wpg));
-        e = launch_batch(g, exact, mask, (const BatchImg *)((char *)sl.dev + off_i[g]),
-                         (const int32_t *)((char *)sl.dev + off_t[g]), (int)tasks[g].size(), grid, wpg, nullptr,
+        if (!ntiles[g]) continue;
+        e = launch_batch(g, exact, mask[g], (const BatchImg *)((char *)sl.dev + off_i[g]),
+                         (const BatchTask *)((char *)sl.dev + off_t[g]), (int)ntiles[g], grid[g], wpg, nullptr,
                          (const float *)sl.dev, nullptr, sl.stream);
         if (e != hipSuccess) return fail_hip(e, "server batch launch");
     }

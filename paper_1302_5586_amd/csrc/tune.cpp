@@ -24,8 +24,15 @@ namespace {
 constexpr int kKinds = 3;  // PF_KIND_2D, PF_KIND_SEP, PF_KIND_U8
 constexpr int kSizes = 3;
 
+// Workgroups per compute unit of a persistent batch launch. One (four
+// waves, one per SIMD) measured best on MI355X: the fewest tiles in flight
+// keep the window of HBM pages the batch touches at once compact.
+constexpr int kBatchBlocksPerCu = 1;
+constexpr int kBatchBlocksPerCuMax = 8;
+
 struct Table {
     pf_tune_entry e[kKinds][PF_R_MAX + 1][kSizes];
+    int batch_blocks_per_cu = kBatchBlocksPerCu;
 };
 
 pf_tune_entry default_entry(int kind, int r, int sc) {
@@ -84,6 +91,11 @@ bool parse_number(const std::string &obj, const char *key, double *out) {
 pf_tune_entry tune_lookup(int kind, int r, int64_t pixels) {
     std::lock_guard<std::mutex> lk(g_mu);
     return g_table.e[kind][r][size_class(pixels)];
+}
+
+int tune_batch_blocks_per_cu() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_table.batch_blocks_per_cu;
 }
 
 // ---------------------------------------------------------------- autotune
@@ -156,8 +168,7 @@ pf_status time_batch_class(int kind, int r, int h, int w, int n, int by, const f
     const int var = kind == PF_KIND_SEP ? PF_VAR_SEPARABLE : PF_VAR_DIRECT;
     const int mask = batch_mask(g, 1 << var);
     std::vector<BatchImg> imgs(n);
-    std::vector<int32_t> tasks;
-    const int sy = (h + by - 1) / by, sx = (w + strip_width(r) - 1) / strip_width(r);
+    int64_t ntiles = 0;
     for (int i = 0; i < n; ++i) {
         BatchImg &d = imgs[i];
         d.in_off = d.out_off = (int64_t)i * h * w;
@@ -167,13 +178,14 @@ pf_status time_batch_class(int kind, int r, int h, int w, int n, int by, const f
         d.r = r;
         d.var = var;
         d.by = by;
-        d.strips_y = sy;
-        d.task_base = (int32_t)tasks.size();
-        d.pad = 0;
-        tasks.insert(tasks.end(), (size_t)sx * sy, i);
+        ntiles += set_strips(d);
     }
+    const int wpg = 4;
+    const int grid = batch_grid(g, false, mask, wpg, ntiles);
+    std::vector<BatchTask> tasks;
+    for (int i = 0; i < n; ++i) append_tiles(tasks, i, imgs[i]);
     void *dev = nullptr;
-    const size_t bi = imgs.size() * sizeof(BatchImg), bt = tasks.size() * 4;
+    const size_t bi = imgs.size() * sizeof(BatchImg), bt = tasks.size() * sizeof(BatchTask);
     hipError_t e = hipMalloc(&dev, bi + bt);
     if (e != hipSuccess) return fail_hip(e, "autotune descriptors");
     e = hipMemcpy(dev, imgs.data(), bi, hipMemcpyHostToDevice);
@@ -182,12 +194,9 @@ pf_status time_batch_class(int kind, int r, int h, int w, int n, int by, const f
     if (e != hipSuccess) {
         st = fail_hip(e, "autotune descriptors");
     } else {
-        const int wpg = 4;
-        const int grid = (int)std::min<int64_t>(((int64_t)tasks.size() + wpg - 1) / wpg,
-                                                batch_grid_limit(g, false, mask, wpg));
         st = time_launch(
             [&](int) {
-                return launch_batch(g, false, mask, (const BatchImg *)dev, (const int32_t *)((char *)dev + bi),
+                return launch_batch(g, false, mask, (const BatchImg *)dev, (const BatchTask *)((char *)dev + bi),
                                     (int)tasks.size(), grid, wpg, in, filt, out, s);
             },
             1, reps, 5, s, us);
@@ -246,7 +255,8 @@ pf_status pf_tune_save(const char *path) {
     FILE *f = fopen(path, "w");
     if (!f) return fail(PF_EINVAL, std::string("cannot write ") + path);
     const DevInfo &d = dev_info();
-    fprintf(f, "{\n  \"library\": \"%s\",\n  \"device_arch\": \"%s\",\n  \"entries\": [\n", pf_version(), d.arch.c_str());
+    fprintf(f, "{\n  \"library\": \"%s\",\n  \"device_arch\": \"%s\",\n  \"batch_blocks_per_cu\": %d,\n  \"entries\": [\n",
+            pf_version(), d.arch.c_str(), t.batch_blocks_per_cu);
     bool first = true;
     for (int k = 0; k < kKinds; ++k)
         for (int r = 0; r <= PF_R_MAX; ++r)
@@ -305,7 +315,29 @@ pf_status pf_tune_load(const char *path) {
         es.push_back(e);
         p = b + 1;
     }
-    return pf_tune_set((int32_t)es.size(), es.data());
+    // Optional: workgroups per compute unit of batch launches.
+    double bpc = kBatchBlocksPerCu;
+    const size_t hdr = text.find("\"batch_blocks_per_cu\"");
+    if (hdr != std::string::npos && hdr < arr) {
+        if (!parse_number(text.substr(hdr, arr - hdr), "batch_blocks_per_cu", &bpc) || bpc < 1 ||
+            bpc > kBatchBlocksPerCuMax)
+            return fail(PF_EINVAL, "bad batch_blocks_per_cu in tune file");
+    }
+    const pf_status st = pf_tune_set((int32_t)es.size(), es.data());
+    if (st != PF_OK) return st;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table.batch_blocks_per_cu = (int)bpc;
+    return PF_OK;
+}
+
+pf_status pf_tune_batch_blocks(int32_t blocks_per_cu, int32_t *previous) {
+    clear_error();
+    if (blocks_per_cu < 0 || blocks_per_cu > kBatchBlocksPerCuMax)
+        return fail(PF_EINVAL, "blocks_per_cu outside 0.." + std::to_string(kBatchBlocksPerCuMax));
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (previous) *previous = g_table.batch_blocks_per_cu;
+    if (blocks_per_cu > 0) g_table.batch_blocks_per_cu = blocks_per_cu;
+    return PF_OK;
 }
 
 pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
@@ -328,8 +360,22 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
         (he = hipMalloc(&filt, 4096)) != hipSuccess) {
         st = fail_hip(he, "autotune allocation");
     } else {
-        (void)hipMemsetAsync(in, 0, big * 4 * nrot, s);
-        (void)hipMemsetAsync(filt, 0, 4096, s);
+        // Timing data: pseudo-random pixels in [0, 1) and small taps. All-zero
+        // buffers time markedly faster on MI355X than real data, and would
+        // steer the table.
+        std::vector<float> host(big);
+        uint32_t x = 0x9e3779b9u;
+        for (size_t i = 0; i < big; ++i) {
+            x ^= x << 13;
+            x ^= x >> 17;
+            x ^= x << 5;
+            host[i] = (float)(x >> 8) * (1.0f / 16777216.0f);
+        }
+        for (int i = 0; i < nrot && he == hipSuccess; ++i)
+            he = hipMemcpy(in + (size_t)i * big, host.data(), big * 4, hipMemcpyHostToDevice);
+        std::vector<float> taps(1024, 1.0f / 17.0f);
+        if (he == hipSuccess) he = hipMemcpy(filt, taps.data(), 4096, hipMemcpyHostToDevice);
+        if (he != hipSuccess) st = fail_hip(he, "autotune data upload");
     }
     for (int sc = 0; sc < kSizes && st == PF_OK; ++sc) {
         for (int kind = 0; kind < kKinds && st == PF_OK; ++kind) {
@@ -429,6 +475,24 @@ pf_status pf_batch_autotune(int32_t n, const int32_t *__restrict h, const int32_
     for (int i = 0; i < n; ++i) present[size_class((int64_t)h[i] * w[i])] = true;
     float best = 0.0f;
     pf_status st = measure(&best);
+    // Workgroups per compute unit first (the whole batch moves together).
+    for (int bpc = 1; bpc <= 4 && st == PF_OK; ++bpc) {
+        int keep = 0;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            keep = g_table.batch_blocks_per_cu;
+            if (bpc == keep) continue;
+            g_table.batch_blocks_per_cu = bpc;
+        }
+        float us = 0.0f;
+        st = measure(&us);
+        if (st == PF_OK && us < 0.97f * best) {
+            best = us;
+        } else {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_table.batch_blocks_per_cu = keep;
+        }
+    }
     const int bys[] = {8, 16, 32, 64};
     // Coordinate descent: one size class at a time, every radius and both
     // FP32 kinds of that class move together; a new tile height is kept

@@ -153,3 +153,27 @@ def test_binding_rejects_host_tensors():
     x = torch.zeros(4, 4)
     with pytest.raises(ValueError):
         pf.filter2d(x, torch.zeros(3, 3))
+
+
+def test_tune_batch_blocks_roundtrip(lib, tmp_path):
+    pf.tune_reset()
+    assert pf.tune_batch_blocks() == 1
+    assert pf.tune_batch_blocks(3) == 1
+    assert pf.tune_batch_blocks() == 3
+    path = str(tmp_path / "tune.json")
+    pf.tune_save(path)
+    assert json.load(open(path))["batch_blocks_per_cu"] == 3
+    pf.tune_reset()
+    assert pf.tune_batch_blocks() == 1
+    pf.tune_load(path)
+    assert pf.tune_batch_blocks() == 3
+    with pytest.raises(pf.PFInvalid):
+        pf.tune_batch_blocks(9)
+    doc = json.load(open(path))
+    doc["batch_blocks_per_cu"] = 0
+    bad = str(tmp_path / "bad.json")
+    json.dump(doc, open(bad, "w"))
+    with pytest.raises(pf.PFInvalid):
+        pf.tune_load(bad)
+    pf.tune_reset()
+    assert pf.tune_batch_blocks() == 1
