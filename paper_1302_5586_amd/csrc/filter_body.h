@@ -77,6 +77,17 @@ __device__ __forceinline__ void st(T *p, T v) {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
+// base + 4 * off as a pointer into global memory. The sum is formed as an
+// integer (a descriptor may carry an absolute address with a null base), so
+// the result is cast through the global address space: from a plain integer
+// the compiler could not tell global from LDS and would emit flat accesses,
+// whose completion waits drain every outstanding load.
+template <class T>
+__device__ __forceinline__ T *global_at(T *base, int64_t off) {
+    typedef __attribute__((address_space(1))) T gT;
+    return (T *)(gT *)(reinterpret_cast<uintptr_t>(base) + (uint64_t)off * 4u);
+}
+
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
@@ -592,9 +603,9 @@ __global__ __launch_bounds__(512) void k_batch_f32(const BatchImg *__restrict__ 
         tile_xy(uniform(tk.tile), d.strips_x, d.strips_y, sx, sy);
         const int y0 = sy * d.by;
         const int rows = min(d.by, d.h - y0);
-        const float *src = reinterpret_cast<const float *>(reinterpret_cast<uintptr_t>(in) + (uint64_t)d.in_off * 4u);
-        float *dst = reinterpret_cast<float *>(reinterpret_cast<uintptr_t>(out) + (uint64_t)d.out_off * 4u);
-        const float *fa = reinterpret_cast<const float *>(reinterpret_cast<uintptr_t>(filt) + (uint64_t)d.filt_off * 4u);
+        const float *src = global_at(in, d.in_off);
+        float *dst = global_at(out, d.out_off);
+        const float *fa = global_at(filt, d.filt_off);
         const float *fb = fa + 2 * d.r + 1;
         // Only the variants in VMASK are compiled in: the register budget of
         // the kernel is the largest of its bodies.
