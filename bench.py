@@ -63,6 +63,19 @@ KERNEL_SOURCES = ("paper_1302_5586_amd/csrc/filter_body.h", "paper_1302_5586_amd
                   "paper_1302_5586_amd/csrc/launch.hip")
 
 
+def kernel_source_hash():
+    """Hash of the kernel sources with comments and blank lines removed
+    (comment edits do not invalidate the counters)."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        text = open(os.path.join(ROOT, f)).read()
+        lines = [re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines()]
+        h.update("\n".join(ln for ln in lines if ln).encode())
+    return h.hexdigest()[:16]
+
+
 def committed_traffic(tag):
     """HBM bytes per launch of a kernel from the committed counter profile
     (profiles/counters.json), or None when the kernel sources changed since
@@ -72,10 +85,7 @@ def committed_traffic(tag):
     if not os.path.exists(path):
         return None
     doc = json.load(open(path))
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    if doc.get("source_hash") != h.hexdigest()[:16]:
+    if doc.get("source_hash") != kernel_source_hash():
         return None
     k = doc.get("kernels", {}).get(tag)
     return None if k is None else k.get("traffic_bytes")

@@ -6,16 +6,25 @@
 // lane in any order. The paper's own code generation targets OpenCL through
 // polyhedral tiling; these kernels are written directly for CDNA4 instead:
 //
-//  * A wave owns a strip of 64 lanes x 4 columns. The outermost lanes on
-//    each side only load halo columns; the inner lanes each produce 4
-//    output columns. Horizontal neighbours come from the adjacent lanes
-//    through DPP wavefront shifts (v_mov_b32_dpp wave_shr/wave_shl), so
-//    the halo never passes through LDS or a second global load.
-//  * The wave walks down its strip one input row at a time (one 16-byte
-//    load per lane per row). Each input row is folded into the 2r+1
-//    output rows it touches, held in a ring of register accumulators, so
-//    every input element is read from memory once per strip and vertical
-//    halo rows are re-read only at strip ends.
+//  * A wave owns a strip of 64 lanes x 4 columns. For radii 1 and 2 every
+//    lane produces 4 outputs (256 columns, 1 KiB of FP32 per row) and the
+//    two outermost lanes also load the r columns beyond the strip; for
+//    larger radii the outermost lane on each side (two for r > 4) only
+//    loads halo columns. Horizontal neighbours come from the adjacent
+//    lanes through DPP wavefront shifts (v_mov_b32_dpp wave_shr/wave_shl),
+//    so the halo never passes through LDS.
+//  * The wave walks down its strip (one 16-byte load per lane per row),
+//    in chunks of rows that are loaded one chunk ahead of the arithmetic.
+//    Each input row is folded into the 2r+1 output rows it touches, held
+//    in a ring of register accumulators with compile-time slot indices, so
+//    every input element is read once per tile and vertical halo rows are
+//    re-read only at tile ends.
+//  * Strips are loaded in one of three branch-free modes: interior (plain
+//    16-byte loads), edge (the nearest in-bounds 16 bytes, each clamped
+//    column picked from them) and tiny (images narrower than 4 columns).
+//    Stores of edge strips and of halo lanes go through buffer resources
+//    whose range check drops the out-of-image columns. Outputs are stored
+//    non-temporal.
 //  * Taps are accumulated per output in the definition's order (dy outer,
 //    dx inner, ascending). By default each tap is one fused multiply-add;
 //    the EXACT instantiation uses a separate multiply and add (this file is
@@ -31,8 +40,7 @@
 //    every wave exits on its own.
 //
 // Workgroup ids are remapped so that consecutive tiles land on the same
-// XCD (workgroups are dealt round-robin over the 8 XCDs), which keeps the
-// rows shared by vertically adjacent strips in one L2.
+// XCD (workgroups are dealt round-robin over the 8 XCDs).
 #pragma once
 
 #include <type_traits>
