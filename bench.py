@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--autotune", default="",
                     help="tune the table (per class, then on the batch workload), write it to this path, and "
                          "bench with it")
-    ap.add_argument("--skip", default="", help="comma list of sections to skip: plain,large,rgb,serve,cpu")
+    ap.add_argument("--skip", default="", help="comma list of sections to skip: plain,large,chain,rgb,serve,cpu")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 512 MiB device copy 4 times (reference for counter scaling)")
     return ap.parse_args()
@@ -257,6 +257,44 @@ def main():
                             "workload": "4096x4096 FP32, 5x5 Gaussian sigma 1.5, seed 1, buffers rotated over 1 GiB"}
             log("%s: %.2f us/call, %.0f GB/s (%.1f%% of HBM)" % (name, ms * 1e3, gbs, 100 * gbs / HBM_PEAK_GBS))
         del xs, os_
+
+    # ---- chain: 4 passes of a 3x3 Gaussian over 4096x4096, fused ----------------
+    if "chain" not in skip:
+        cfg = synth.config_large()
+        n = cfg.h * cfg.w
+        passes = 4
+        nbuf = 8
+        xs = [torch.from_numpy(cfg.image).to(dev) for _ in range(nbuf)]
+        os_ = [torch.empty_like(xs[0]) for _ in range(nbuf)]
+        tmp = [torch.empty_like(xs[0]) for _ in range(2)]
+        f3 = torch.from_numpy(synth.gaussian_2d(1, 1.0)).to(dev)
+
+        def fused(i):
+            pf.filter_chain(xs[i % nbuf], f3, passes, pf.BORDER_CLAMP, out=os_[i % nbuf])
+
+        def unfused(i):
+            src = xs[i % nbuf]
+            for p in range(passes):
+                dst = os_[i % nbuf] if p == passes - 1 else tmp[p % 2]
+                pf.filter2d(src, f3, out=dst)
+                src = dst
+
+        res = {}
+        for name, fn in (("fused", fused), ("unfused", unfused)):
+            for i in range(nbuf):
+                fn(i)
+            res[name] = time_events(torch, fn, 32, stream)
+        gbs = 8 * n / (res["fused"] * 1e-3) / 1e9
+        result["chain"] = {"value": round(n * passes / (res["fused"] * 1e-3) / 1e9, 3),
+                           "unit": "Gpixel-passes/s", "us_per_chain": round(res["fused"] * 1e3, 2),
+                           "unfused_us_per_chain": round(res["unfused"] * 1e3, 2),
+                           "speedup_vs_unfused": round(res["unfused"] / res["fused"], 3),
+                           "achieved_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                           "workload": "4096x4096 FP32 (seed 1), 4 passes of a 3x3 Gaussian sigma 1.0, clamp; "
+                                       "fused (one launch) vs 4 single-pass launches"}
+        log("chain: fused %.2f us, unfused %.2f us (x%.2f), %.0f GB/s (%.1f%% of HBM)" % (
+            res["fused"] * 1e3, res["unfused"] * 1e3, res["unfused"] / res["fused"], gbs, 100 * gbs / HBM_PEAK_GBS))
+        del xs, os_, tmp
 
     # ---- 1080p RGB uint8 7x7 -------------------------------------------------
     if "rgb" not in skip:

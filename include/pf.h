@@ -86,6 +86,15 @@ typedef int32_t pf_status;
 #define PF_VAR_SEPARABLE   1  /* fused row pass + column pass (PF_KIND_SEP only)  */
 #define PF_VAR_SEP_DIRECT  2  /* PF_KIND_SEP run as 2D taps fy[i]*fx[j] (FP32)    */
 
+/* Border rules: the value an index outside [0, n) of an axis reads. */
+#define PF_BORDER_CLAMP    0  /* nearest edge element: a a | a b c | c c           */
+#define PF_BORDER_ZERO     1  /* zero                                              */
+#define PF_BORDER_REFLECT  2  /* edge repeated, period 2n: b a | a b c | c b       */
+#define PF_BORDER_MIRROR   3  /* edge not repeated, period 2n-2: c b | a b c | b a  */
+
+/* Largest r * passes of a filter chain (the halo one LDS tile carries). */
+#define PF_CHAIN_HALO_MAX 16
+
 const char *pf_status_str(pf_status s);
 /* Message of the last failing call on this thread ("" if none). The string
  * stays valid until the next pf_* call on the same thread. */
@@ -103,6 +112,35 @@ pf_status pf_filter2d_f32(int32_t h, int32_t w, int32_t r,
                           PF_ARR(const float, filt, (2 * r + 1) * (2 * r + 1)),
                           PF_ARR(float, out, h * w),
                           int32_t flags, void *stream);
+
+/* ---- single image: FP32 full 2D under a border rule ---------------------
+ * As pf_filter2d_f32, with the image extended past its edges by `border`
+ * (PF_BORDER_*); each axis is mapped on its own, so a corner reads the
+ * element both mappings select. Stencil codes of the image-processing and
+ * fluid-dynamics domains (Sec. I) use all four rules. PF_BORDER_CLAMP runs
+ * the same kernel as pf_filter2d_f32; the other rules run the chain kernel
+ * with one pass (r * 1 <= PF_CHAIN_HALO_MAX). Unknown rule: PF_EINVAL. */
+pf_status pf_filter2d_f32_border(int32_t h, int32_t w, int32_t r, int32_t border,
+                                 PF_ARR(const float, in, h * w),
+                                 PF_ARR(const float, filt, (2 * r + 1) * (2 * r + 1)),
+                                 PF_ARR(float, out, h * w),
+                                 int32_t flags, void *stream);
+
+/* ---- single image: chain of FP32 2D passes, fused ------------------------
+ * `passes` >= 1 applications of the same filter: pass p filters the FP32
+ * image of pass p-1 (the input for p = 1) extended by `border`, and `out`
+ * receives the last. All passes run in one kernel over LDS tiles that carry
+ * a halo of r * passes (<= PF_CHAIN_HALO_MAX, else PF_EUNSUPPORTED): the
+ * intermediate images never reach HBM. This is the composition of stencil
+ * kernels that cross-component optimisation targets (Sec. II). With
+ * PF_FLAG_EXACT every pass is the sequential definition bit for bit; by
+ * default each tap is one fused multiply-add. Same buffer rules as
+ * pf_filter2d_f32. */
+pf_status pf_filter_chain_f32(int32_t h, int32_t w, int32_t r, int32_t passes, int32_t border,
+                              PF_ARR(const float, in, h * w),
+                              PF_ARR(const float, filt, (2 * r + 1) * (2 * r + 1)),
+                              PF_ARR(float, out, h * w),
+                              int32_t flags, void *stream);
 
 /* ---- single image: FP32 separable ---------------------------------------
  * Row pass with fx, FP32 intermediate, column pass with fy, fused in one

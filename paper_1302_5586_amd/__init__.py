@@ -31,6 +31,8 @@ BATCH_GRAPH = 0x2
 BATCH_NO_TUNE = 0x4
 KIND_2D, KIND_SEP, KIND_U8 = 0, 1, 2
 VAR_DIRECT, VAR_SEPARABLE, VAR_SEP_DIRECT = 0, 1, 2
+BORDER_CLAMP, BORDER_ZERO, BORDER_REFLECT, BORDER_MIRROR = 0, 1, 2, 3
+CHAIN_HALO_MAX = 16
 
 
 class PFError(RuntimeError):
@@ -92,6 +94,8 @@ _SIGS = {
     "pf_version": (ctypes.c_char_p, []),
     "pf_filter2d_f32": (_I32, [_I32, _I32, _I32, _P, _P, _P, _I32, _P]),
     "pf_filter_sep_f32": (_I32, [_I32, _I32, _I32, _P, _P, _P, _P, _I32, _P]),
+    "pf_filter2d_f32_border": (_I32, [_I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
+    "pf_filter_chain_f32": (_I32, [_I32, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
     "pf_filter2d_u8": (_I32, [_I32, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
     "pf_filter_f32_shaped": (_I32, [_I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
     "pf_tune_lookup": (_I32, [_I32, _I32, _I64, ctypes.POINTER(TuneEntry)]),
@@ -207,6 +211,40 @@ def filter2d(x, f, *, exact: bool = False, out=None, stream=None):
     _dev_tensor(out, torch.float32, "out", (2,))
     _check(load().pf_filter2d_f32(h, w, r, x.data_ptr(), f.data_ptr(), out.data_ptr(),
                                   FLAG_EXACT if exact else 0, _stream_ptr(stream)))
+    return out
+
+
+def filter2d_border(x, f, border: int, *, exact: bool = False, out=None, stream=None):
+    """FP32 2D correlation of ``x`` [H, W] with ``f`` under a border rule (BORDER_*)."""
+    torch = _torch()
+    _dev_tensor(x, torch.float32, "x", (2,))
+    _dev_tensor(f, torch.float32, "f", (2,))
+    if f.shape[0] != f.shape[1]:
+        raise ValueError("filter must be square")
+    r = _radius_of(f.shape[0], "filter")
+    h, w = x.shape
+    if out is None:
+        out = torch.empty_like(x)
+    _dev_tensor(out, torch.float32, "out", (2,))
+    _check(load().pf_filter2d_f32_border(h, w, r, border, x.data_ptr(), f.data_ptr(), out.data_ptr(),
+                                         FLAG_EXACT if exact else 0, _stream_ptr(stream)))
+    return out
+
+
+def filter_chain(x, f, passes: int, border: int = 0, *, exact: bool = False, out=None, stream=None):
+    """``passes`` fused applications of the 2D filter ``f`` to ``x`` [H, W] (one kernel)."""
+    torch = _torch()
+    _dev_tensor(x, torch.float32, "x", (2,))
+    _dev_tensor(f, torch.float32, "f", (2,))
+    if f.shape[0] != f.shape[1]:
+        raise ValueError("filter must be square")
+    r = _radius_of(f.shape[0], "filter")
+    h, w = x.shape
+    if out is None:
+        out = torch.empty_like(x)
+    _dev_tensor(out, torch.float32, "out", (2,))
+    _check(load().pf_filter_chain_f32(h, w, r, passes, border, x.data_ptr(), f.data_ptr(), out.data_ptr(),
+                                      FLAG_EXACT if exact else 0, _stream_ptr(stream)))
     return out
 
 

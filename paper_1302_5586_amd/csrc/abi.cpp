@@ -131,6 +131,36 @@ pf_status pf_filter2d_f32(int32_t h, int32_t w, int32_t r, const float *in, cons
                    stream);
 }
 
+pf_status pf_filter_chain_f32(int32_t h, int32_t w, int32_t r, int32_t passes, int32_t border, const float *in,
+                              const float *filt, float *out, int32_t flags, void *stream) {
+    clear_error();
+    pf_status st = check_image(h, w, r);
+    if (st) return st;
+    if ((st = check_f32_bufs(h, w, in, out))) return st;
+    if (flags & ~PF_FLAG_EXACT) return fail(PF_EINVAL, "unknown flags");
+    if (border < PF_BORDER_CLAMP || border > PF_BORDER_MIRROR)
+        return fail(PF_EINVAL, "unknown border rule " + std::to_string(border));
+    if (passes < 1) return fail(PF_EINVAL, "passes must be >= 1");
+    if ((int64_t)r * passes > PF_CHAIN_HALO_MAX)
+        return fail(PF_EUNSUPPORTED, "r * passes = " + std::to_string((int64_t)r * passes) + " exceeds " +
+                                         std::to_string(PF_CHAIN_HALO_MAX));
+    if (!filt) return fail(PF_EINVAL, "null filter pointer");
+    if ((uintptr_t)filt % 4) return fail(PF_EINVAL, "filters must be 4-byte aligned");
+    const int k = 2 * r + 1;
+    if (overlap(filt, (size_t)k * k * sizeof(float), out, (size_t)h * (size_t)w * sizeof(float)))
+        return fail(PF_EALIAS, "filter and output overlap (restrict)");
+    hipError_t e = launch_chain(r, (flags & PF_FLAG_EXACT) != 0, in, filt, out, h, w, passes, border,
+                                (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "kernel launch");
+    return PF_OK;
+}
+
+pf_status pf_filter2d_f32_border(int32_t h, int32_t w, int32_t r, int32_t border, const float *in, const float *filt,
+                                 float *out, int32_t flags, void *stream) {
+    if (border == PF_BORDER_CLAMP) return pf_filter2d_f32(h, w, r, in, filt, out, flags, stream);
+    return pf_filter_chain_f32(h, w, r, 1, border, in, filt, out, flags, stream);
+}
+
 pf_status pf_filter_sep_f32(int32_t h, int32_t w, int32_t r, const float *in, const float *fx, const float *fy,
                             float *out, int32_t flags, void *stream) {
     clear_error();

@@ -1,0 +1,332 @@
+// Chains of 2D filter passes fused per tile, under four border rules.
+//
+// A chain applies the same (2r+1)^2 filter `passes` times; pass p reads the
+// FP32 image pass p-1 produced, with that image extended past its edges by
+// the border rule. Composing several stencil passes into one kernel is the
+// cross-component optimisation the paper motivates (Sec. II), for the
+// image-processing and fluid-dynamics stencil domains it names (Sec. I);
+// every pass keeps the independent-iteration semantics of Sec. II-B.3.
+//
+// Design (time tiling in LDS): a workgroup owns a 64 x 32 output tile. It
+// loads the tile plus a halo of H = r * passes rows and columns once from
+// HBM, border-extended on load. Pass p computes, from the LDS image of pass
+// p-1, every in-image position within H - p*r of the tile, then writes the
+// border extension of its own result into the out-of-image positions of
+// that region (interior tiles have none). Reads of a pass therefore never
+// need index arithmetic for borders, and only the last pass goes to HBM:
+// 8 bytes of HBM traffic per pixel for the whole chain instead of 8 per
+// pass. The price is recomputing the halo ring, which shrinks by r per
+// pass.
+//
+// Arithmetic per output: taps in definition order (dy outer, dx inner,
+// ascending), one FMA per tap, or with EXACT a separate FP32 multiply and
+// add (built with -ffp-contract=off), which reproduces the sequential
+// program bit for bit at every pass.
+#include "pf_internal.h"
+
+namespace pf {
+namespace chain {
+
+constexpr int kTileX = 64, kTileY = 32, kThreads = 256;
+
+// Source index of position i of an axis of n elements under a border rule;
+// -1 where the rule reads a zero.
+__device__ __forceinline__ int border_index(int i, int n, int border) {
+    if (i >= 0 && i < n) return i;
+    if (border == PF_BORDER_CLAMP) return i < 0 ? 0 : n - 1;
+    if (border == PF_BORDER_ZERO) return -1;
+    if (border == PF_BORDER_REFLECT) {  // period 2n, edge repeated: d c b a | a b c d | d c b a
+        const int p = 2 * n;
+        int m = i % p;
+        if (m < 0) m += p;
+        return m < n ? m : p - 1 - m;
+    }
+    if (n == 1) return 0;  // PF_BORDER_MIRROR: period 2n-2, edge not repeated
+    const int p = 2 * n - 2;
+    int m = i % p;
+    if (m < 0) m += p;
+    return m < n ? m : p - m;
+}
+
+template <bool EXACT>
+__device__ __forceinline__ float madd(float wgt, float x, float acc) {
+    if constexpr (EXACT) {
+        const float prod = wgt * x;
+        return acc + prod;
+    } else {
+        return __builtin_fmaf(wgt, x, acc);
+    }
+}
+
+__device__ __forceinline__ int xcd_remap(int b, int g) {
+    const int xcd = b & 7, idx = b >> 3;
+    const int per = g >> 3, rem = g & 7;
+    return xcd * per + min(xcd, rem) + idx;
+}
+
+// LDS layout: one image of (kTileY + 2H) rows and `pitch` floats per row.
+// Image column ox (= x0 - H) sits at buffer column pad(R), a multiple of 4
+// that is >= R, so the 4-output task at any 4-aligned buffer column c reads
+// its window [c - R, c + 3 + R] as 16-byte aligned LDS vectors starting at
+// c - pad(R), and consecutive lanes read consecutive 16-byte blocks (no
+// bank conflicts).
+__host__ __device__ constexpr int lds_pad(int r) { return 4 * ((r + 3) / 4); }
+__host__ __device__ constexpr int lds_pitch(int r, int halo) {
+    return (2 * lds_pad(r) + kTileX + 2 * halo + 4 + 3) / 4 * 4;
+}
+__host__ __device__ constexpr int lds_rows(int halo) { return kTileY + 2 * halo + 4; }
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Linear task index -> (row, column) over a rows x n grid, stepping by
+// kThreads without a division per step.
+struct Walk {
+    int row, col, drow, dcol, n;
+    __device__ __forceinline__ Walk(int start, int n_) : n(n_) {
+        row = start / n;
+        col = start - row * n;
+        drow = kThreads / n;
+        dcol = kThreads - drow * n;
+    }
+    __device__ __forceinline__ void next() {
+        row += drow;
+        col += dcol;
+        if (col >= n) {
+            col -= n;
+            ++row;
+        }
+    }
+};
+
+// Loads the rows x W0 input region at image (oy, ox) into the buffer.
+// Loads go out in batches of kBatch per thread before any is waited for:
+// one HBM latency per batch instead of one per element. BORDER: some
+// positions lie outside the image and read through the border rule.
+template <bool BORDER>
+__device__ __forceinline__ void load_region(const float *__restrict__ in, float *buf, int h, int w, int oy, int ox,
+                                            int rows, int W0, int pitch, int cx, int border) {
+    constexpr int kBatch = 16;
+    const int total = rows * W0;
+    Walk t(threadIdx.x, W0);
+    for (int i0 = threadIdx.x; i0 < total; i0 += kBatch * kThreads) {
+        float v[kBatch];
+        int at[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const bool ok = i0 + u * kThreads < total;
+            const int y = oy + t.row, x = ox + t.col;
+            at[u] = ok ? t.row * pitch + x + cx : -1;
+            int64_t src;
+            if constexpr (BORDER) {
+                const int yy = border_index(y, h, border), xx = border_index(x, w, border);
+                src = (yy < 0 || xx < 0 || !ok) ? -1 : (int64_t)yy * w + xx;
+            } else {
+                src = ok ? (int64_t)y * w + x : -1;
+            }
+            v[u] = src >= 0 ? in[src] : 0.0f;
+            t.next();
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+            if (at[u] >= 0) buf[at[u]] = v[u];
+    }
+}
+
+// Tasks one thread holds in registers over a pass (a task: 4 x 4 outputs):
+// the largest pass region has at most kTileX / 4 + 2 * ceil((H - R) / 4) + 2
+// column blocks and (kTileY + 2 (H - R)) / 4 + 1 row blocks, H <=
+// PF_CHAIN_HALO_MAX.
+constexpr int kMaxTasks = ((kTileX / 4 + 2 * ((PF_CHAIN_HALO_MAX + 3) / 4) + 2) *
+                               ((kTileY + 2 * PF_CHAIN_HALO_MAX) / 4 + 1) +
+                           kThreads - 1) /
+                          kThreads;
+
+template <int R, bool EXACT>
+__global__ __launch_bounds__(kThreads) void k_chain_f32(const float *__restrict__ in, const float *__restrict__ filt,
+                                                        float *__restrict__ out, int h, int w, int passes, int border,
+                                                        int tiles_x, int ntiles) {
+    constexpr int K = 2 * R + 1;
+    constexpr int PAD = lds_pad(R);
+    constexpr int NB = 1 + 2 * PAD / 4;  // 16-byte blocks per window row
+    extern __shared__ float lds[];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int H = R * passes;
+    const int pitch = lds_pitch(R, H), rows = lds_rows(H);
+    const int W0 = kTileX + 2 * H;
+    float *buf = lds;
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int x0 = tx * kTileX, y0 = ty * kTileY;
+    // Buffer (0, PAD) holds image position (oy, ox) = (y0 - H, x0 - H).
+    const int ox = x0 - H, oy = y0 - H;
+    const int cx = PAD - ox;  // buffer column of image column x is x + cx
+    const bool interior = ox >= 0 && oy >= 0 && x0 + kTileX + H <= w && y0 + kTileY + H <= h;
+
+    // Pass 0: the input region, border-extended.
+    if (interior)
+        load_region<false>(in, buf, h, w, oy, ox, rows - 4, W0, pitch, cx, border);
+    else
+        load_region<true>(in, buf, h, w, oy, ox, rows - 4, W0, pitch, cx, border);
+    __syncthreads();
+
+    // One LDS image: a pass computes its whole region into registers, and
+    // only after a barrier overwrites the previous pass's image with it.
+    for (int p = 1; p <= passes; ++p) {
+        const bool last = p == passes;
+        const int m = (passes - p) * R;  // reach of pass p's region beyond the tile
+        const int ylo = max(y0 - m, 0), yhi = min(y0 + kTileY + m, h);
+        const int xlo = max(x0 - m, 0), xhi = min(x0 + kTileX + m, w);
+        // Tasks: 4 x 4 outputs, rows from ylo in steps of 4, columns at
+        // 4-aligned buffer columns covering [xlo, xhi). Window reads stay
+        // inside the buffer: columns from c - PAD >= 0 (c >= xlo + cx >= PAD +
+        // H - m) to c + 3 + PAD < pitch, rows from ylo - R - oy >= H - m - R
+        // >= 0 to at most yhi + 3 + R - oy < rows (4 spare rows). Outputs
+        // outside [ylo, yhi) x [xlo, xhi) are computed from whatever the
+        // buffer holds there and never stored.
+        const int cb0 = (xlo + cx) >> 2, cb1 = ((xhi - 1 + cx) >> 2) + 1;
+        const int ncb = cb1 - cb0, ntask = ((yhi - ylo + 3) >> 2) * ncb;
+        float res[kMaxTasks][4][4];
+        int at_y[kMaxTasks], at_c[kMaxTasks];
+        Walk t(threadIdx.x, ncb);
+#pragma unroll
+        for (int u = 0; u < kMaxTasks; ++u) {
+            at_y[u] = ylo + 4 * t.row;
+            at_c[u] = 4 * (cb0 + t.col);
+            t.next();
+            if (threadIdx.x + u * kThreads >= ntask) continue;
+            const float *base = buf + (at_y[u] - R - oy) * pitch + (at_c[u] - PAD);
+            float acc[4][4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[j][k] = 0.0f;
+            // Input row i of the window feeds output rows j = i - dy; rows
+            // come in ascending order, so each output takes dy ascending.
+#pragma unroll
+            for (int i = 0; i < 4 + 2 * R; ++i) {
+                float v[4 * NB];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const f4 q = *reinterpret_cast<const f4 *>(base + i * pitch + 4 * b);
+                    v[4 * b] = q.x;
+                    v[4 * b + 1] = q.y;
+                    v[4 * b + 2] = q.z;
+                    v[4 * b + 3] = q.w;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int dy = i - j;
+                    if (dy < 0 || dy >= K) continue;
+#pragma unroll
+                    for (int dx = 0; dx < K; ++dx) {
+                        const float wt = filt[dy * K + dx];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) acc[j][k] = madd<EXACT>(wt, v[PAD - R + k + dx], acc[j][k]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) res[u][j][k] = acc[j][k];
+        }
+        if (last) {
+#pragma unroll
+            for (int u = 0; u < kMaxTasks; ++u) {
+                if (threadIdx.x + u * kThreads >= ntask) continue;
+                const int x = at_c[u] - cx;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int y = at_y[u] + j;
+                    if (y >= yhi) continue;
+                    float *o = out + (int64_t)y * w;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (x + k >= xlo && x + k < xhi) __builtin_nontemporal_store(res[u][j][k], o + x + k);
+                }
+            }
+            break;
+        }
+        __syncthreads();  // every read of the previous image is done
+#pragma unroll
+        for (int u = 0; u < kMaxTasks; ++u) {
+            if (threadIdx.x + u * kThreads >= ntask) continue;
+            const int x = at_c[u] - cx;
+            const bool full = x >= xlo && x + 3 < xhi;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int y = at_y[u] + j;
+                if (y >= yhi) continue;
+                float *o = buf + (y - oy) * pitch + at_c[u];
+                if (full) {
+                    f4 q;
+                    q.x = res[u][j][0];
+                    q.y = res[u][j][1];
+                    q.z = res[u][j][2];
+                    q.w = res[u][j][3];
+                    *reinterpret_cast<f4 *>(o) = q;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (x + k >= xlo && x + k < xhi) o[k] = res[u][j][k];
+                }
+            }
+        }
+        __syncthreads();
+        if (!interior) {
+            // Border extension of pass p's image over the out-of-image
+            // positions that pass p+1 reads: those of its region within R of
+            // the image. Each source lies in the in-image part just written:
+            // a rule maps a position within R of an edge to within R of it
+            // (m >= R here), or wraps inside an image narrower than a tile,
+            // which a single tile covers.
+            const int ya = max(y0 - m, -R), yb = min(y0 + kTileY + m, h + R);
+            const int xa = max(x0 - m, -R), xb = min(x0 + kTileX + m, w + R);
+            Walk f(threadIdx.x, xb - xa);
+            for (int i = threadIdx.x; i < (yb - ya) * (xb - xa); i += kThreads, f.next()) {
+                const int y = ya + f.row, x = xa + f.col;
+                if (y >= 0 && y < h && x >= 0 && x < w) continue;
+                const int yy = border_index(y, h, border), xx = border_index(x, w, border);
+                buf[(y - oy) * pitch + x + cx] = (yy < 0 || xx < 0) ? 0.0f : buf[(yy - oy) * pitch + xx + cx];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int R, bool EXACT>
+hipError_t launch_r(const float *in, const float *filt, float *out, int h, int w, int passes, int border,
+                    hipStream_t s) {
+    const int H = R * passes;
+    const int tiles_x = (w + kTileX - 1) / kTileX, tiles_y = (h + kTileY - 1) / kTileY;
+    const int64_t ntiles = (int64_t)tiles_x * tiles_y;
+    if (ntiles > INT32_MAX) return hipErrorInvalidValue;
+    const size_t lds = (size_t)lds_rows(H) * lds_pitch(R, H) * sizeof(float);
+    hipLaunchKernelGGL((k_chain_f32<R, EXACT>), dim3((unsigned)ntiles), dim3(kThreads), lds, s, in, filt, out, h, w,
+                       passes, border, tiles_x, (int)ntiles);
+    return hipGetLastError();
+}
+
+}  // namespace chain
+
+hipError_t launch_chain(int r, bool exact, const float *in, const float *filt, float *out, int h, int w, int passes,
+                        int border, hipStream_t s) {
+#define PF_CH(R) \
+    return exact ? chain::launch_r<R, true>(in, filt, out, h, w, passes, border, s) \
+                 : chain::launch_r<R, false>(in, filt, out, h, w, passes, border, s)
+    switch (r) {
+        case 0: PF_CH(0);
+        case 1: PF_CH(1);
+        case 2: PF_CH(2);
+        case 3: PF_CH(3);
+        case 4: PF_CH(4);
+        case 5: PF_CH(5);
+        case 6: PF_CH(6);
+        case 7: PF_CH(7);
+        case 8: PF_CH(8);
+        default: return hipErrorInvalidValue;
+    }
+#undef PF_CH
+}
+
+}  // namespace pf

@@ -98,6 +98,10 @@ hipError_t launch_u8(int r, const uint8_t *in, const int8_t *filt, uint8_t *out,
 hipError_t launch_batch(int group, bool exact, int mask, const BatchImg *imgs, const BatchTask *tasks,
                         int ntasks, int grid, int wpg, const float *in, const float *filt, float *out,
                         hipStream_t s);
+// Fused chain of `passes` 2D passes under a border rule (chain.hip); also
+// the single-pass filter for borders other than clamp.
+hipError_t launch_chain(int r, bool exact, const float *in, const float *filt, float *out, int h, int w, int passes,
+                        int border, hipStream_t s);
 // Workgroups of the batch kernel that fit on the device at once.
 int batch_grid_limit(int group, bool exact, int mask, int wpg);
 void *batch_kernel_fn(int group, bool exact, int mask);

@@ -177,3 +177,25 @@ def test_tune_batch_blocks_roundtrip(lib, tmp_path):
         pf.tune_load(bad)
     pf.tune_reset()
     assert pf.tune_batch_blocks() == 1
+
+
+def test_chain_and_border_validation(lib):
+    def chain(h=8, w=8, r=1, passes=2, border=pf.BORDER_CLAMP, inp=FAKE, filt=FAKE + 4096, out=FAKE + (1 << 20),
+              flags=0):
+        return lib.pf_filter_chain_f32(h, w, r, passes, border, inp, filt, out, flags, None)
+    assert chain(passes=0) == pf.PF_EINVAL
+    assert chain(border=4) == pf.PF_EINVAL
+    assert chain(border=-1) == pf.PF_EINVAL
+    assert chain(flags=0x2) == pf.PF_EINVAL
+    assert chain(filt=0) == pf.PF_EINVAL
+    assert chain(h=0) == pf.PF_EINVAL
+    assert chain(r=9) == pf.PF_EINVAL
+    assert chain(r=4, passes=5) == pf.PF_EUNSUPPORTED      # halo 20 > PF_CHAIN_HALO_MAX
+    assert chain(r=1, passes=17) == pf.PF_EUNSUPPORTED
+    assert chain(out=FAKE) == pf.PF_EALIAS
+    assert chain(filt=FAKE + (1 << 20) + 4) == pf.PF_EALIAS
+    assert lib.pf_filter2d_f32_border(8, 8, 1, 7, FAKE, FAKE + 4096, FAKE + (1 << 20), 0, None) == pf.PF_EINVAL
+    assert lib.pf_filter2d_f32_border(8, 8, 9, pf.BORDER_ZERO, FAKE, FAKE + 4096, FAKE + (1 << 20), 0,
+                                      None) == pf.PF_EINVAL
+    assert lib.pf_filter2d_f32_border(8, 8, 1, pf.BORDER_REFLECT, FAKE, FAKE + 4096, FAKE, 0,
+                                      None) == pf.PF_EALIAS
