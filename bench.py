@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--autotune", default="",
                     help="tune the table (per class, then on the batch workload), write it to this path, and "
                          "bench with it")
-    ap.add_argument("--skip", default="", help="comma list of sections to skip: plain,large,chain,rgb,serve,cpu")
+    ap.add_argument("--skip", default="", help="comma list of sections to skip: plain,large,chain,reduce,rgb,serve,cpu")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 512 MiB device copy 4 times (reference for counter scaling)")
     return ap.parse_args()
@@ -295,6 +295,41 @@ def main():
         log("chain: fused %.2f us, unfused %.2f us (x%.2f), %.0f GB/s (%.1f%% of HBM)" % (
             res["fused"] * 1e3, res["unfused"] * 1e3, res["unfused"] / res["fused"], gbs, 100 * gbs / HBM_PEAK_GBS))
         del xs, os_, tmp
+
+    # ---- reductions: sum/mean of 4096x4096 FP32, histogram of 256 MiB uint8 ----
+    if "reduce" not in skip:
+        cfg = synth.config_large()
+        n = cfg.h * cfg.w
+        nbuf = 8
+        xs = [torch.from_numpy(cfg.image).to(dev).reshape(-1) for _ in range(nbuf)]
+        outs = torch.empty(2, dtype=torch.float64, device=dev)
+        ws = pf._workspace(pf.load().pf_sum_workspace, n, dev)
+        fn = lambda i: pf.sum_f32(xs[i % nbuf], out=outs, workspace=ws)  # noqa: E731
+        for i in range(nbuf):
+            fn(i)
+        ms_sum = time_events(torch, fn, 64, stream)
+        del xs
+        nb = 256 << 20
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(5)
+        xb = torch.randint(0, 256, (nb,), dtype=torch.uint8, device=dev, generator=gen)
+        hout = torch.empty(256, dtype=torch.int64, device=dev)
+        hws = pf._workspace(pf.load().pf_hist_workspace, nb, dev)
+        fn = lambda i: pf.hist256_u8(xb, out=hout, workspace=hws)  # noqa: E731
+        fn(0)
+        ms_hist = time_events(torch, fn, 16, stream)
+        del xb
+        sum_gbs = 4 * n / (ms_sum * 1e-3) / 1e9
+        hist_gbs = nb / (ms_hist * 1e-3) / 1e9
+        result["reduce"] = {"sum_us": round(ms_sum * 1e3, 2), "sum_GBs": round(sum_gbs, 1),
+                            "sum_frac_hbm": round(sum_gbs / HBM_PEAK_GBS, 4),
+                            "hist_us": round(ms_hist * 1e3, 2), "hist_GBs": round(hist_gbs, 1),
+                            "hist_frac_hbm": round(hist_gbs / HBM_PEAK_GBS, 4),
+                            "workload": "float64 sum and mean of 4096x4096 FP32 (seed 1, 8 rotating buffers); "
+                                        "256-bin histogram of 256 MiB of uniform random bytes (torch seed 5)"}
+        log("reduce: sum %.2f us (%.0f GB/s, %.1f%%), hist %.2f us (%.0f GB/s, %.1f%%)" % (
+            ms_sum * 1e3, sum_gbs, 100 * sum_gbs / HBM_PEAK_GBS, ms_hist * 1e3, hist_gbs,
+            100 * hist_gbs / HBM_PEAK_GBS))
 
     # ---- 1080p RGB uint8 7x7 -------------------------------------------------
     if "rgb" not in skip:

@@ -142,6 +142,30 @@ pf_status pf_filter_chain_f32(int32_t h, int32_t w, int32_t r, int32_t passes, i
                               PF_ARR(float, out, h * w),
                               int32_t flags, void *stream);
 
+/* ---- reductions: sum and mean of an FP32 array ---------------------------
+ * The `reduction` directive (Sec. II-B.3) and OptiML's sum lowered to a
+ * loop with a reduction (Sec. III-B). out[0] = sum of x[0..n) and out[1] =
+ * out[0] / n, in float64. Reproducible (Sec. III-A's concern): a fixed
+ * summation tree, the same bits on every call and launch. n >= 1, at most
+ * 2^40. x: float[n] device, 4-byte aligned. out: double[2] device, 8-byte
+ * aligned. workspace: device memory of at least pf_sum_workspace(n) bytes,
+ * 8-byte aligned, owned by the caller, no initial contents needed; calls
+ * sharing one workspace must not overlap in time. Overlap between x, out
+ * and workspace: PF_EALIAS. Two launches on `stream`, no allocation. */
+pf_status pf_sum_workspace(int64_t n, PF_OUTP(size_t, bytes));
+pf_status pf_sum_f32(int64_t n, PF_ARR(const float, x, n), PF_ARR(double, out, 2),
+                     void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---- reductions: 256-bin histogram of a uint8 array ----------------------
+ * The indirect increment A[t[i]]++ of the `independent` example
+ * (Sec. II-B.3) with repeated indices: hist[v] = number of i with
+ * x[i] == v. Exact. n >= 1, at most 2^40. x: uint8_t[n] device (any
+ * alignment). hist: int64_t[256] device, 8-byte aligned. workspace: at
+ * least pf_hist_workspace(n) bytes, 4-byte aligned, as for pf_sum_f32. */
+pf_status pf_hist_workspace(int64_t n, PF_OUTP(size_t, bytes));
+pf_status pf_hist256_u8(int64_t n, PF_ARR(const uint8_t, x, n), PF_ARR(int64_t, hist, 256),
+                        void *workspace, size_t workspace_bytes, void *stream);
+
 /* ---- single image: FP32 separable ---------------------------------------
  * Row pass with fx, FP32 intermediate, column pass with fy, fused in one
  * kernel: the intermediate never reaches memory (the cross-kernel fusion

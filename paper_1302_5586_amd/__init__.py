@@ -95,6 +95,10 @@ _SIGS = {
     "pf_filter2d_f32": (_I32, [_I32, _I32, _I32, _P, _P, _P, _I32, _P]),
     "pf_filter_sep_f32": (_I32, [_I32, _I32, _I32, _P, _P, _P, _P, _I32, _P]),
     "pf_filter2d_f32_border": (_I32, [_I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
+    "pf_sum_workspace": (_I32, [_I64, _P]),
+    "pf_sum_f32": (_I32, [_I64, _P, _P, _P, ctypes.c_size_t, _P]),
+    "pf_hist_workspace": (_I32, [_I64, _P]),
+    "pf_hist256_u8": (_I32, [_I64, _P, _P, _P, ctypes.c_size_t, _P]),
     "pf_filter_chain_f32": (_I32, [_I32, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
     "pf_filter2d_u8": (_I32, [_I32, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
     "pf_filter_f32_shaped": (_I32, [_I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
@@ -245,6 +249,44 @@ def filter_chain(x, f, passes: int, border: int = 0, *, exact: bool = False, out
     _dev_tensor(out, torch.float32, "out", (2,))
     _check(load().pf_filter_chain_f32(h, w, r, passes, border, x.data_ptr(), f.data_ptr(), out.data_ptr(),
                                       FLAG_EXACT if exact else 0, _stream_ptr(stream)))
+    return out
+
+
+def _workspace(fn, n, dev):
+    torch = _torch()
+    nb = ctypes.c_size_t(0)
+    _check(fn(n, ctypes.byref(nb)))
+    return torch.empty(max((nb.value + 7) // 8, 1), dtype=torch.float64, device=dev)
+
+
+def sum_f32(x, *, out=None, workspace=None, stream=None):
+    """Reproducible float64 sum and mean of a contiguous FP32 tensor:
+    returns a device float64 tensor [sum, mean]."""
+    torch = _torch()
+    if not x.is_cuda or x.dtype != torch.float32 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous CUDA float32 tensor")
+    n = x.numel()
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=x.device)
+    if workspace is None:
+        workspace = _workspace(load().pf_sum_workspace, n, x.device)
+    _check(load().pf_sum_f32(n, x.data_ptr(), out.data_ptr(), workspace.data_ptr(),
+                             workspace.numel() * workspace.element_size(), _stream_ptr(stream)))
+    return out
+
+
+def hist256_u8(x, *, out=None, workspace=None, stream=None):
+    """256-bin histogram (int64 counts) of a contiguous uint8 tensor."""
+    torch = _torch()
+    if not x.is_cuda or x.dtype != torch.uint8 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous CUDA uint8 tensor")
+    n = x.numel()
+    if out is None:
+        out = torch.empty(256, dtype=torch.int64, device=x.device)
+    if workspace is None:
+        workspace = _workspace(load().pf_hist_workspace, n, x.device)
+    _check(load().pf_hist256_u8(n, x.data_ptr(), out.data_ptr(), workspace.data_ptr(),
+                                workspace.numel() * workspace.element_size(), _stream_ptr(stream)))
     return out
 
 

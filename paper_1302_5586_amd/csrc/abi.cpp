@@ -155,6 +155,62 @@ pf_status pf_filter_chain_f32(int32_t h, int32_t w, int32_t r, int32_t passes, i
     return PF_OK;
 }
 
+static const int64_t kReduceMax = (int64_t)1 << 40;
+
+pf_status pf_sum_workspace(int64_t n, size_t *bytes) {
+    clear_error();
+    if (!bytes) return fail(PF_EINVAL, "null output");
+    if (n < 1 || n > kReduceMax) return fail(PF_EINVAL, "n must be in 1..2^40");
+    *bytes = sum_workspace_bytes(n);
+    return PF_OK;
+}
+
+pf_status pf_sum_f32(int64_t n, const float *x, double *out, void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (n < 1 || n > kReduceMax) return fail(PF_EINVAL, "n must be in 1..2^40");
+    if (!x || !out || !workspace) return fail(PF_EINVAL, "null pointer");
+    if ((uintptr_t)x % 4) return fail(PF_EINVAL, "x must be 4-byte aligned");
+    if (((uintptr_t)out | (uintptr_t)workspace) % 8) return fail(PF_EINVAL, "out and workspace must be 8-byte aligned");
+    const size_t need = sum_workspace_bytes(n);
+    if (workspace_bytes < need)
+        return fail(PF_EINVAL, "workspace of " + std::to_string(workspace_bytes) + " bytes, " + std::to_string(need) +
+                                   " needed");
+    const size_t xb = (size_t)n * sizeof(float);
+    if (overlap(x, xb, out, 2 * sizeof(double)) || overlap(x, xb, workspace, need) ||
+        overlap(out, 2 * sizeof(double), workspace, need))
+        return fail(PF_EALIAS, "x, out and workspace must not overlap (restrict)");
+    hipError_t e = launch_sum(x, n, out, workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "kernel launch");
+    return PF_OK;
+}
+
+pf_status pf_hist_workspace(int64_t n, size_t *bytes) {
+    clear_error();
+    if (!bytes) return fail(PF_EINVAL, "null output");
+    if (n < 1 || n > kReduceMax) return fail(PF_EINVAL, "n must be in 1..2^40");
+    *bytes = hist_workspace_bytes(n);
+    return PF_OK;
+}
+
+pf_status pf_hist256_u8(int64_t n, const uint8_t *x, int64_t *hist, void *workspace, size_t workspace_bytes,
+                        void *stream) {
+    clear_error();
+    if (n < 1 || n > kReduceMax) return fail(PF_EINVAL, "n must be in 1..2^40");
+    if (!x || !hist || !workspace) return fail(PF_EINVAL, "null pointer");
+    if ((uintptr_t)hist % 8) return fail(PF_EINVAL, "hist must be 8-byte aligned");
+    if ((uintptr_t)workspace % 4) return fail(PF_EINVAL, "workspace must be 4-byte aligned");
+    const size_t need = hist_workspace_bytes(n);
+    if (workspace_bytes < need)
+        return fail(PF_EINVAL, "workspace of " + std::to_string(workspace_bytes) + " bytes, " + std::to_string(need) +
+                                   " needed");
+    if (overlap(x, (size_t)n, hist, 256 * sizeof(int64_t)) || overlap(x, (size_t)n, workspace, need) ||
+        overlap(hist, 256 * sizeof(int64_t), workspace, need))
+        return fail(PF_EALIAS, "x, hist and workspace must not overlap (restrict)");
+    hipError_t e = launch_hist(x, n, hist, workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "kernel launch");
+    return PF_OK;
+}
+
 pf_status pf_filter2d_f32_border(int32_t h, int32_t w, int32_t r, int32_t border, const float *in, const float *filt,
                                  float *out, int32_t flags, void *stream) {
     if (border == PF_BORDER_CLAMP) return pf_filter2d_f32(h, w, r, in, filt, out, flags, stream);

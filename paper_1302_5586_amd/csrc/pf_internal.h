@@ -102,6 +102,12 @@ hipError_t launch_batch(int group, bool exact, int mask, const BatchImg *imgs, c
 // the single-pass filter for borders other than clamp.
 hipError_t launch_chain(int r, bool exact, const float *in, const float *filt, float *out, int h, int w, int passes,
                         int border, hipStream_t s);
+// Reductions (reduce.hip): workspace sizes and the two-launch sum and
+// histogram.
+size_t sum_workspace_bytes(int64_t n);
+size_t hist_workspace_bytes(int64_t n);
+hipError_t launch_sum(const float *x, int64_t n, double *out, void *workspace, hipStream_t s);
+hipError_t launch_hist(const uint8_t *x, int64_t n, int64_t *hist, void *workspace, hipStream_t s);
 // Workgroups of the batch kernel that fit on the device at once.
 int batch_grid_limit(int group, bool exact, int mask, int wpg);
 void *batch_kernel_fn(int group, bool exact, int mask);

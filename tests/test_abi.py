@@ -199,3 +199,23 @@ def test_chain_and_border_validation(lib):
                                       None) == pf.PF_EINVAL
     assert lib.pf_filter2d_f32_border(8, 8, 1, pf.BORDER_REFLECT, FAKE, FAKE + 4096, FAKE, 0,
                                       None) == pf.PF_EALIAS
+
+
+def test_reduce_validation(lib):
+    import ctypes
+    nb = ctypes.c_size_t(0)
+    assert lib.pf_sum_workspace(0, ctypes.byref(nb)) == pf.PF_EINVAL
+    assert lib.pf_sum_workspace(1 << 41, ctypes.byref(nb)) == pf.PF_EINVAL
+    assert lib.pf_sum_workspace(65537, ctypes.byref(nb)) == pf.PF_OK and nb.value == 2 * 8
+    assert lib.pf_hist_workspace(1, ctypes.byref(nb)) == pf.PF_OK and nb.value == 256 * 4
+    assert lib.pf_hist_workspace(1 << 30, ctypes.byref(nb)) == pf.PF_OK and nb.value == 1024 * 256 * 4
+    ws, out = FAKE + (1 << 30), FAKE + (1 << 31)
+    assert lib.pf_sum_f32(100, FAKE + 2, out, ws, 8, None) == pf.PF_EINVAL       # misaligned x
+    assert lib.pf_sum_f32(100, FAKE, out + 4, ws, 8, None) == pf.PF_EINVAL       # misaligned out
+    assert lib.pf_sum_f32(100, FAKE, out, ws, 4, None) == pf.PF_EINVAL           # workspace too small
+    assert lib.pf_sum_f32(100, FAKE, FAKE + 8, ws, 8, None) == pf.PF_EALIAS      # out inside x
+    assert lib.pf_sum_f32(100, FAKE, out, 0, 8, None) == pf.PF_EINVAL
+    assert lib.pf_hist256_u8(0, FAKE, out, ws, 1024, None) == pf.PF_EINVAL
+    assert lib.pf_hist256_u8(100, FAKE, out + 4, ws, 1024, None) == pf.PF_EINVAL  # misaligned hist
+    assert lib.pf_hist256_u8(100, FAKE, out, ws, 1000, None) == pf.PF_EINVAL      # workspace too small
+    assert lib.pf_hist256_u8(100, FAKE, FAKE + 48, ws, 1024, None) == pf.PF_EALIAS
