@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--autotune", default="",
                     help="tune the table (per class, then on the batch workload), write it to this path, and "
                          "bench with it")
-    ap.add_argument("--skip", default="", help="comma list of sections to skip: plain,large,chain,reduce,rgb,serve,cpu")
+    ap.add_argument("--skip", default="", help="comma list of sections to skip: plain,large,chain,reduce,inc,rgb,serve,cpu")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 512 MiB device copy 4 times (reference for counter scaling)")
     return ap.parse_args()
@@ -330,6 +330,36 @@ def main():
         log("reduce: sum %.2f us (%.0f GB/s, %.1f%%), hist %.2f us (%.0f GB/s, %.1f%%)" % (
             ms_sum * 1e3, sum_gbs, 100 * sum_gbs / HBM_PEAK_GBS, ms_hist * 1e3, hist_gbs,
             100 * hist_gbs / HBM_PEAK_GBS))
+
+    # ---- OP2 edge-to-cell increment on a 2048 x 2048 quad mesh ----------------
+    if "inc" not in skip:
+        m = synth.config_mesh()
+        t0 = time.perf_counter()
+        plan_inc = pf.IncPlan(m.ncells, m.edge_to_cells)
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        ed = torch.from_numpy(m.edge).to(dev)
+        cells = torch.from_numpy(m.cell).to(dev)
+        e2c = torch.from_numpy(m.edge_to_cells.reshape(-1)).to(dev)
+        fn = lambda i: plan_inc.run(ed, cells)  # noqa: E731
+        fn(0)
+        ms_plan = time_events(torch, fn, 50, stream)
+        fn = lambda i: pf.edge_inc_atomic(e2c, ed, cells)  # noqa: E731
+        fn(0)
+        ms_atomic = time_events(torch, fn, 50, stream)
+        # Bytes the plan run must move: each cell read and written (16 B), its
+        # offset (4 B), and per increment an index (4 B) and an edge value (8 B).
+        inc_bytes = 20 * m.ncells + 2 * m.nedges * 12
+        gbs = inc_bytes / (ms_plan * 1e-3) / 1e9
+        result["inc"] = {"value": round(m.nedges / (ms_plan * 1e-3) / 1e9, 3), "unit": "Gedge/s",
+                         "plan_us": round(ms_plan * 1e3, 2), "atomic_us": round(ms_atomic * 1e3, 2),
+                         "plan_build_ms": round(plan_ms, 1), "achieved_GBs": round(gbs, 1),
+                         "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                         "workload": "2048x2048 quad mesh, 4,194,304 cells, 8,384,512 edges, random cell numbering "
+                                     "and edge order (seed 6), float64 values"}
+        log("inc: plan %.2f us (%.0f GB/s, %.1f%%), atomic %.2f us, plan build %.0f ms" % (
+            ms_plan * 1e3, gbs, 100 * gbs / HBM_PEAK_GBS, ms_atomic * 1e3, plan_ms))
+        plan_inc.close()
+        del ed, cells, e2c
 
     # ---- 1080p RGB uint8 7x7 -------------------------------------------------
     if "rgb" not in skip:

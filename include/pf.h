@@ -166,6 +166,37 @@ pf_status pf_hist_workspace(int64_t n, PF_OUTP(size_t, bytes));
 pf_status pf_hist256_u8(int64_t n, PF_ARR(const uint8_t, x, n), PF_ARR(int64_t, hist, 256),
                         void *workspace, size_t workspace_bytes, void *stream);
 
+/* ---- OP2 indirect increment: edges add into cells -----------------------
+ * OP2's op_par_loop over edges with two OP_INC arguments through an
+ * edge-to-cell map (Sec. III-A): for i = 0 .. nedges-1 in order,
+ * cell[map[2i+1]] += edge[i], then cell[map[2i]] += edge[i] (float64).
+ *
+ * Plan path (reproducible, equal to that loop bit for bit): the plan
+ * inverts the map once (host copy `edge_to_cells`, int32[2 * nedges],
+ * read during the call only; entries in 0..ncells-1, else PF_EINVAL;
+ * nedges <= 2^30) and keeps its tables in device memory until destroyed.
+ * pf_inc_plan_run adds every cell's increments in the loop's order, one
+ * thread per cell: edge: double[nedges] device, cell: double[ncells]
+ * device (read and written), 8-byte aligned, disjoint (else PF_EALIAS);
+ * sizes must match the plan's. */
+typedef struct pf_inc_plan pf_inc_plan;
+pf_status pf_inc_plan_create(int32_t ncells, int32_t nedges,
+                             PF_ARR(const int32_t, edge_to_cells, 2 * nedges),
+                             PF_OUTP(pf_inc_plan *, plan));
+pf_status pf_inc_plan_run(const pf_inc_plan *plan, int32_t ncells, int32_t nedges,
+                          PF_ARR(const double, edge, nedges), PF_ARR(double, cell, ncells),
+                          void *stream);
+pf_status pf_inc_plan_destroy(pf_inc_plan *plan);
+
+/* Atomic path: one launch, float64 atomic adds, no plan. The map is a
+ * device array (int32[2 * nedges], 4-byte aligned); entries outside
+ * 0..ncells-1 are skipped. The order of a cell's increments varies from
+ * run to run, so results agree with the loop only to rounding. */
+pf_status pf_edge_inc_atomic_f64(int32_t ncells, int32_t nedges,
+                                 PF_ARR(const int32_t, edge_to_cells, 2 * nedges),
+                                 PF_ARR(const double, edge, nedges), PF_ARR(double, cell, ncells),
+                                 void *stream);
+
 /* ---- single image: FP32 separable ---------------------------------------
  * Row pass with fx, FP32 intermediate, column pass with fy, fused in one
  * kernel: the intermediate never reaches memory (the cross-kernel fusion

@@ -203,7 +203,7 @@ def hist256_u8(x) -> np.ndarray:
 
 
 def edge_inc_f64(ncells: int, edge_to_cells, edge_data, cell_data) -> np.ndarray:
-    """For each edge i in order: cell[e2c[2i]] += edge[i]; cell[e2c[2i+1]] += edge[i]."""
+    """For each edge i in order: cell[e2c[2i+1]] += edge[i], then cell[e2c[2i]] += edge[i]."""
     e2c = np.ascontiguousarray(edge_to_cells, dtype=np.int32).ravel()
     ed = np.ascontiguousarray(edge_data, dtype=np.float64).ravel()
     cells = np.array(cell_data, dtype=np.float64, copy=True).ravel()

@@ -96,6 +96,10 @@ _SIGS = {
     "pf_filter_sep_f32": (_I32, [_I32, _I32, _I32, _P, _P, _P, _P, _I32, _P]),
     "pf_filter2d_f32_border": (_I32, [_I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
     "pf_sum_workspace": (_I32, [_I64, _P]),
+    "pf_inc_plan_create": (_I32, [_I32, _I32, _P, _P]),
+    "pf_inc_plan_run": (_I32, [_P, _I32, _I32, _P, _P, _P]),
+    "pf_inc_plan_destroy": (_I32, [_P]),
+    "pf_edge_inc_atomic_f64": (_I32, [_I32, _I32, _P, _P, _P, _P]),
     "pf_sum_f32": (_I32, [_I64, _P, _P, _P, ctypes.c_size_t, _P]),
     "pf_hist_workspace": (_I32, [_I64, _P]),
     "pf_hist256_u8": (_I32, [_I64, _P, _P, _P, ctypes.c_size_t, _P]),
@@ -288,6 +292,57 @@ def hist256_u8(x, *, out=None, workspace=None, stream=None):
     _check(load().pf_hist256_u8(n, x.data_ptr(), out.data_ptr(), workspace.data_ptr(),
                                 workspace.numel() * workspace.element_size(), _stream_ptr(stream)))
     return out
+
+
+class IncPlan:
+    """OP2-style edge-to-cell increment plan (see pf_inc_plan_create):
+    ``run(edge, cell)`` adds every edge value into its two cells, in the
+    sequential loop's order, bit for bit."""
+
+    def __init__(self, ncells: int, edge_to_cells):
+        m = _i32(np.asarray(edge_to_cells).reshape(-1))
+        if m.size % 2:
+            raise ValueError("edge_to_cells needs two cells per edge")
+        self.ncells, self.nedges = int(ncells), m.size // 2
+        h = ctypes.c_void_p()
+        _check(load().pf_inc_plan_create(self.ncells, self.nedges, _np_ptr(m), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, edge, cell, stream=None):
+        torch = _torch()
+        for t, name, n in ((edge, "edge", self.nedges), (cell, "cell", self.ncells)):
+            if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n:
+                raise ValueError("%s must be a contiguous CUDA float64 tensor of %d elements" % (name, n))
+        _check(load().pf_inc_plan_run(self._h, self.ncells, self.nedges, edge.data_ptr(), cell.data_ptr(),
+                                      _stream_ptr(stream)))
+        return cell
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pf_inc_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def edge_inc_atomic(edge_to_cells, edge, cell, stream=None):
+    """Edge-to-cell increment with float64 atomics (device map int32 [2 * nedges])."""
+    torch = _torch()
+    if not edge_to_cells.is_cuda or edge_to_cells.dtype != torch.int32 or not edge_to_cells.is_contiguous():
+        raise ValueError("edge_to_cells must be a contiguous CUDA int32 tensor")
+    nedges = edge_to_cells.numel() // 2
+    for t, name in ((edge, "edge"), (cell, "cell")):
+        if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous CUDA float64 tensor" % name)
+    if edge.numel() != nedges:
+        raise ValueError("edge must have one value per edge")
+    _check(load().pf_edge_inc_atomic_f64(cell.numel(), nedges, edge_to_cells.data_ptr(), edge.data_ptr(),
+                                         cell.data_ptr(), _stream_ptr(stream)))
+    return cell
 
 
 def filter_sep(x, fx, fy, *, exact: bool = False, out=None, stream=None):

@@ -200,3 +200,36 @@ def arrival_trace(rate: float = 2000.0, duration: float = 60.0, seed: int = 4,
 def serve_pool(n: int = 1024, seed: int = 40, with_pixels: bool = True) -> BatchF32:
     """Device-resident image pool for the served stream (sizes as the batch)."""
     return batch_f32(n, seed, with_pixels=with_pixels)
+
+
+@dataclass
+class QuadMesh:
+    """An unstructured-looking mesh: the cells of an nx x ny grid of quads,
+    numbered by a random permutation, and one edge per pair of cells that
+    share a face, listed in random order with its two cells in random
+    order. Edge values are float64 draws."""
+    ncells: int
+    nedges: int
+    edge_to_cells: np.ndarray  # int32 [nedges, 2]
+    edge: np.ndarray           # float64 [nedges]
+    cell: np.ndarray           # float64 [ncells], initial cell values
+
+
+def quad_mesh(nx: int, ny: int, seed: int) -> QuadMesh:
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(nx * ny).astype(np.int64)
+    ids = perm.reshape(ny, nx)
+    horiz = np.stack([ids[:, :-1].reshape(-1), ids[:, 1:].reshape(-1)], axis=1)
+    vert = np.stack([ids[:-1, :].reshape(-1), ids[1:, :].reshape(-1)], axis=1)
+    e2c = np.concatenate([horiz, vert])
+    e2c = e2c[rng.permutation(len(e2c))]
+    flip = rng.random(len(e2c)) < 0.5
+    e2c[flip] = e2c[flip][:, ::-1]
+    edge = rng.standard_normal(len(e2c))
+    cell = rng.standard_normal(nx * ny)
+    return QuadMesh(nx * ny, len(e2c), np.ascontiguousarray(e2c, dtype=np.int32), edge, cell)
+
+
+def config_mesh() -> QuadMesh:
+    """2048 x 2048 quads: 4,194,304 cells and 8,384,512 edges, seed 6."""
+    return quad_mesh(2048, 2048, 6)

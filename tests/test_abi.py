@@ -219,3 +219,20 @@ def test_reduce_validation(lib):
     assert lib.pf_hist256_u8(100, FAKE, out + 4, ws, 1024, None) == pf.PF_EINVAL  # misaligned hist
     assert lib.pf_hist256_u8(100, FAKE, out, ws, 1000, None) == pf.PF_EINVAL      # workspace too small
     assert lib.pf_hist256_u8(100, FAKE, FAKE + 48, ws, 1024, None) == pf.PF_EALIAS
+
+
+def test_inc_validation(lib):
+    import ctypes
+    import numpy as np
+    h = ctypes.c_void_p()
+    bad = np.array([0, 5], np.int32)
+    assert lib.pf_inc_plan_create(5, 1, bad.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)) == pf.PF_EINVAL
+    assert lib.pf_inc_plan_create(0, 0, None, ctypes.byref(h)) == pf.PF_EINVAL
+    assert lib.pf_inc_plan_create(5, -1, None, ctypes.byref(h)) == pf.PF_EINVAL
+    assert lib.pf_inc_plan_create(5, (1 << 30) + 1, bad.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.byref(h)) == pf.PF_EUNSUPPORTED
+    assert lib.pf_inc_plan_run(None, 5, 1, FAKE, FAKE + 4096, None) == pf.PF_EINVAL
+    assert lib.pf_inc_plan_destroy(None) == pf.PF_OK
+    assert lib.pf_edge_inc_atomic_f64(0, 1, FAKE, FAKE + 64, FAKE + 4096, None) == pf.PF_EINVAL
+    assert lib.pf_edge_inc_atomic_f64(4, 1, FAKE + 2, FAKE + 64, FAKE + 4096, None) == pf.PF_EINVAL
+    assert lib.pf_edge_inc_atomic_f64(4, 2, FAKE, FAKE + 64, FAKE + 8, None) == pf.PF_EALIAS
