@@ -77,6 +77,7 @@ __host__ __device__ constexpr int lds_pitch(int r, int halo) {
 __host__ __device__ constexpr int lds_rows(int halo) { return kTileY + 2 * halo + 4; }
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 
 // Linear task index -> (row, column) over a rows x n grid, stepping by
 // kThreads without a division per step.
@@ -235,14 +236,26 @@ __global__ __launch_bounds__(kThreads) void k_chain_f32(const float *__restrict_
             for (int u = 0; u < kMaxTasks; ++u) {
                 if (threadIdx.x + u * kThreads >= ntask) continue;
                 const int x = at_c[u] - cx;
+                const bool full = x >= xlo && x + 3 < xhi;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int y = at_y[u] + j;
                     if (y >= yhi) continue;
                     float *o = out + (int64_t)y * w;
+                    if (full) {
+                        // One 16-byte store per row: a wave's lanes cover whole
+                        // cache lines (rows need only 4-byte alignment).
+                        f4u q;
+                        q.x = res[u][j][0];
+                        q.y = res[u][j][1];
+                        q.z = res[u][j][2];
+                        q.w = res[u][j][3];
+                        __builtin_nontemporal_store(q, reinterpret_cast<f4u *>(o + x));
+                    } else {
 #pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (x + k >= xlo && x + k < xhi) __builtin_nontemporal_store(res[u][j][k], o + x + k);
+                        for (int k = 0; k < 4; ++k)
+                            if (x + k >= xlo && x + k < xhi) __builtin_nontemporal_store(res[u][j][k], o + x + k);
+                    }
                 }
             }
             break;

@@ -28,7 +28,7 @@ constexpr int kThreads = 256;
 constexpr int64_t kChunk = 65536;  // elements per chunk partial (fixed: part of the definition of the result)
 constexpr int kSumBlocks = 2048;   // most blocks of the partial-sum launch
 constexpr int kHistBlocks = 1024;  // most blocks (sub-histograms) of the histogram launch
-constexpr int64_t kHistSpan = 1 << 20;  // bytes per histogram block task
+constexpr int64_t kHistSpan = 1 << 18;  // bytes per histogram block task
 
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 
@@ -160,13 +160,22 @@ __global__ __launch_bounds__(kThreads) void k_hist_partial(const uint8_t *__rest
     }
 }
 
-// hist[v] = sum over blocks of sub[b][v].
-__global__ __launch_bounds__(256) void k_hist_final(const uint32_t *__restrict__ sub, int nblocks,
-                                                    int64_t *__restrict__ hist) {
-    const int v = threadIdx.x;
+// hist[v] = sum over blocks of sub[b][v]: one workgroup per bin, its 256
+// threads over the blocks, then a tree in LDS (integers: exact in any order).
+__global__ __launch_bounds__(kThreads) void k_hist_final(const uint32_t *__restrict__ sub, int nblocks,
+                                                         int64_t *__restrict__ hist) {
+    __shared__ int64_t s[kThreads];
+    const int v = blockIdx.x;
     int64_t acc = 0;
-    for (int b = 0; b < nblocks; ++b) acc += sub[(int64_t)b * 256 + v];
-    hist[v] = acc;
+    for (int b = threadIdx.x; b < nblocks; b += kThreads) acc += sub[(int64_t)b * 256 + v];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int half = kThreads / 2; half > 0; half >>= 1) {
+        if ((int)threadIdx.x < half) s[threadIdx.x] += s[threadIdx.x + half];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) hist[v] = s[0];
 }
 
 }  // namespace red
@@ -199,7 +208,7 @@ hipError_t launch_hist(const uint8_t *x, int64_t n, int64_t *hist, void *workspa
     hipLaunchKernelGGL(red::k_hist_partial, dim3(nb), dim3(red::kThreads), 0, s, x, n, sub);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(red::k_hist_final, dim3(1), dim3(256), 0, s, sub, nb, hist);
+    hipLaunchKernelGGL(red::k_hist_final, dim3(256), dim3(red::kThreads), 0, s, sub, nb, hist);
     return hipGetLastError();
 }
 
