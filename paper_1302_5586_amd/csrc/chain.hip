@@ -48,6 +48,14 @@ __device__ __forceinline__ int border_index(int i, int n, int border) {
     return m < n ? m : p - m;
 }
 
+// Workgroup barrier that orders LDS only (a plain __syncthreads() also
+// waits for every global access in flight).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <bool EXACT>
 __device__ __forceinline__ float madd(float wgt, float x, float acc) {
     if constexpr (EXACT) {
@@ -142,34 +150,18 @@ constexpr int kMaxTasks = ((kTileX / 4 + 2 * ((PF_CHAIN_HALO_MAX + 3) / 4) + 2) 
                            kThreads - 1) /
                           kThreads;
 
+// The passes of one tile over its LDS image `buf` (pass 0 already in it):
+// buffer row 0 / column pad(R) holds image position (y0 - H, x0 - H).
 template <int R, bool EXACT>
-__global__ __launch_bounds__(kThreads) void k_chain_f32(const float *__restrict__ in, const float *__restrict__ filt,
-                                                        float *__restrict__ out, int h, int w, int passes, int border,
-                                                        int tiles_x, int ntiles) {
+__device__ __forceinline__ void tile_passes(float *buf, int pitch, const float *__restrict__ filt,
+                                            float *__restrict__ out, int h, int w, int passes, int border, int x0,
+                                            int y0, bool interior) {
     constexpr int K = 2 * R + 1;
     constexpr int PAD = lds_pad(R);
     constexpr int NB = 1 + 2 * PAD / 4;  // 16-byte blocks per window row
-    extern __shared__ float lds[];
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
     const int H = R * passes;
-    const int pitch = lds_pitch(R, H), rows = lds_rows(H);
-    const int W0 = kTileX + 2 * H;
-    float *buf = lds;
-    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-    const int x0 = tx * kTileX, y0 = ty * kTileY;
-    // Buffer (0, PAD) holds image position (oy, ox) = (y0 - H, x0 - H).
     const int ox = x0 - H, oy = y0 - H;
     const int cx = PAD - ox;  // buffer column of image column x is x + cx
-    const bool interior = ox >= 0 && oy >= 0 && x0 + kTileX + H <= w && y0 + kTileY + H <= h;
-
-    // Pass 0: the input region, border-extended.
-    if (interior)
-        load_region<false>(in, buf, h, w, oy, ox, rows - 4, W0, pitch, cx, border);
-    else
-        load_region<true>(in, buf, h, w, oy, ox, rows - 4, W0, pitch, cx, border);
-    __syncthreads();
-
     // One LDS image: a pass computes its whole region into registers, and
     // only after a barrier overwrites the previous pass's image with it.
     for (int p = 1; p <= passes; ++p) {
@@ -260,7 +252,7 @@ __global__ __launch_bounds__(kThreads) void k_chain_f32(const float *__restrict_
             }
             break;
         }
-        __syncthreads();  // every read of the previous image is done
+        lds_barrier();  // every read of the previous image is done
 #pragma unroll
         for (int u = 0; u < kMaxTasks; ++u) {
             if (threadIdx.x + u * kThreads >= ntask) continue;
@@ -285,7 +277,7 @@ __global__ __launch_bounds__(kThreads) void k_chain_f32(const float *__restrict_
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         if (!interior) {
             // Border extension of pass p's image over the out-of-image
             // positions that pass p+1 reads: those of its region within R of
@@ -302,9 +294,33 @@ __global__ __launch_bounds__(kThreads) void k_chain_f32(const float *__restrict_
                 const int yy = border_index(y, h, border), xx = border_index(x, w, border);
                 buf[(y - oy) * pitch + x + cx] = (yy < 0 || xx < 0) ? 0.0f : buf[(yy - oy) * pitch + xx + cx];
             }
-            __syncthreads();
+            lds_barrier();
         }
     }
+}
+
+template <int R, bool EXACT>
+__global__ __launch_bounds__(kThreads) void k_chain_f32(const float *__restrict__ in, const float *__restrict__ filt,
+                                                        float *__restrict__ out, int h, int w, int passes, int border,
+                                                        int tiles_x, int ntiles) {
+    constexpr int PAD = lds_pad(R);
+    extern __shared__ float lds[];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int H = R * passes;
+    const int pitch = lds_pitch(R, H), rows = lds_rows(H);
+    const int W0 = kTileX + 2 * H;
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int x0 = tx * kTileX, y0 = ty * kTileY;
+    const int ox = x0 - H, oy = y0 - H;
+    const bool interior = ox >= 0 && oy >= 0 && x0 + kTileX + H <= w && y0 + kTileY + H <= h;
+    // Pass 0: the input region, border-extended.
+    if (interior)
+        load_region<false>(in, lds, h, w, oy, ox, rows - 4, W0, pitch, PAD - ox, border);
+    else
+        load_region<true>(in, lds, h, w, oy, ox, rows - 4, W0, pitch, PAD - ox, border);
+    __syncthreads();
+    tile_passes<R, EXACT>(lds, pitch, filt, out, h, w, passes, border, x0, y0, interior);
 }
 
 template <int R, bool EXACT>
