@@ -143,8 +143,7 @@ def load() -> ctypes.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libpencilfilter.so is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
-                          "or `python paper_1302_5586_amd/build.py`")
+        raise ImportError("libpencilfilter.so is not built; run `python paper_1302_5586_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
