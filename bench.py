@@ -12,7 +12,8 @@ Printed as one JSON line with, besides the contract fields:
                 average duration from HIP events on its stream, against
                 8 TB/s; `traffic` is filled from committed counter profiles
                 when they match the current kernel, else null;
-  plain         the same 512 images as 512 single-image launches;
+  plain         the same 512 images as 512 single-image launches (from
+                Python, and replayed from a captured graph);
   large_2d / large_sep   the 4096x4096 5x5 Gaussian (2D and fused
                 separable), buffers rotated over 1 GiB;
   chain         4 fused passes of a 3x3 Gaussian over 4096x4096, against 4
@@ -240,6 +241,28 @@ def main():
         result["plain"] = {"value": round(pv, 3), "unit": "Gpixel/s", "ms_per_step": round(ms, 4),
                            "launches_per_step": b.n, "batched_speedup": round(value / pv, 3)}
         log("plain: %.3f ms/step, %.1f Gpx/s (batched x%.2f)" % (ms, pv, value / pv))
+        # The same 512 launches captured once in a graph and replayed: the
+        # GPU-side cost of separate kernels, without the host's per-call work.
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            plain_step(0)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            plain_step(0)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        msg = time_events(torch, lambda _: g.replay(), max(5, args.steps), stream)
+        pg = px / (msg * 1e-3) / 1e9
+        result["plain"]["graph_replay"] = {"value": round(pg, 3), "unit": "Gpixel/s", "ms_per_step": round(msg, 4),
+                                           "batched_speedup": round(value / pg, 3)}
+        log("plain, 512 launches replayed from a graph: %.3f ms/step, %.1f Gpx/s (batched x%.2f)" % (
+            msg, pg, value / pg))
+        del g
 
     # ---- 4096x4096 5x5 Gaussian, plain filter ---------------------------------
     if "large" not in skip:
