@@ -145,9 +145,22 @@ def test_exact_batch_matches_oracle_bitwise():
 def test_config_batch_512():
     """The 512-image batch (seed 3): every image bit-identical to its single
     launch; a sample of 40 images against the oracle element by element; and
-    the full batch against the oracle on sampled pixels of every image."""
+    the full batch against the oracle on sampled pixels of every image.
+    Run with the committed MI355X tune table, the launch configuration the
+    benchmark times."""
     dev = device()
+    import os
     import torch
+    table = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1302_5586_amd",
+                         "tune_mi355x.json")
+    pf.tune_load(table)
+    try:
+        _config_batch_512(dev, torch)
+    finally:
+        pf.tune_reset()
+
+
+def _config_batch_512(dev, torch):
     b = synth.config_batch()
     filts = [np.concatenate([b.fx[i], b.fx[i]]) for i in range(b.n)]
     pk = pf.pack_batch(b.images, filts, [pf.KIND_SEP] * b.n)

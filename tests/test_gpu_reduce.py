@@ -14,7 +14,7 @@ from gpu_util import device
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [1, 3, 4, 5, 1023, 65535, 65536, 65537, 3 * 65536 + 5, 1 << 20]
+SIZES = [1, 3, 4, 5, 1023, 16383, 16384, 16385, 65537, 3 * 65536 + 5, 1 << 20]
 
 
 def _t(a, dev):
