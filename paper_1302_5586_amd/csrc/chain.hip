@@ -107,37 +107,46 @@ struct Walk {
     }
 };
 
-// Loads the rows x W0 input region at image (oy, ox) into the buffer.
-// Loads go out in batches of kBatch per thread before any is waited for:
-// one HBM latency per batch instead of one per element. BORDER: some
-// positions lie outside the image and read through the border rule.
+// Loads the rows x W0 input region at image (oy, ox) into the buffer
+// (region column c at buffer column PAD + c). A lane owns region columns
+// lane and lane + 64 (W0 <= 64 + 2 * PF_CHAIN_HALO_MAX), so their source
+// columns, border-mapped, are found once; wave v takes rows v, v + 4, ...,
+// eight rows (up to 16 loads per lane) in flight before any is waited for.
+// BORDER: some positions lie outside the image and read through the border
+// rule.
 template <bool BORDER>
 __device__ __forceinline__ void load_region(const float *__restrict__ in, float *buf, int h, int w, int oy, int ox,
-                                            int rows, int W0, int pitch, int cx, int border) {
-    constexpr int kBatch = 16;
-    const int total = rows * W0;
-    Walk t(threadIdx.x, W0);
-    for (int i0 = threadIdx.x; i0 < total; i0 += kBatch * kThreads) {
-        float v[kBatch];
-        int at[kBatch];
+                                            int rows, int W0, int pitch, int pad, int border) {
+    constexpr int kRows = 8;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool two = lane + 64 < W0;
+    int sx0 = ox + lane, sx1 = ox + lane + 64;
+    if constexpr (BORDER) {
+        sx0 = border_index(sx0, w, border);
+        sx1 = border_index(sx1, w, border);
+    }
+    float *dst = buf + pad + lane;
+    for (int r0 = wave; r0 < rows; r0 += 4 * kRows) {
+        float v0[kRows], v1[kRows];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const bool ok = i0 + u * kThreads < total;
-            const int y = oy + t.row, x = ox + t.col;
-            at[u] = ok ? t.row * pitch + x + cx : -1;
-            int64_t src;
-            if constexpr (BORDER) {
-                const int yy = border_index(y, h, border), xx = border_index(x, w, border);
-                src = (yy < 0 || xx < 0 || !ok) ? -1 : (int64_t)yy * w + xx;
-            } else {
-                src = ok ? (int64_t)y * w + x : -1;
-            }
-            v[u] = src >= 0 ? in[src] : 0.0f;
-            t.next();
+        for (int u = 0; u < kRows; ++u) {
+            const int r = r0 + 4 * u;
+            int sy = oy + r;
+            if constexpr (BORDER) sy = border_index(sy, h, border);
+            const bool row_ok = r < rows && sy >= 0;
+            const float *src = in + (int64_t)sy * w;
+            v0[u] = v1[u] = 0.0f;
+            if (row_ok && (!BORDER || sx0 >= 0)) v0[u] = src[sx0];
+            if (row_ok && two && (!BORDER || sx1 >= 0)) v1[u] = src[sx1];
         }
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u)
-            if (at[u] >= 0) buf[at[u]] = v[u];
+        for (int u = 0; u < kRows; ++u) {
+            const int r = r0 + 4 * u;
+            if (r >= rows) break;
+            dst[r * pitch] = v0[u];
+            if (two) dst[r * pitch + 64] = v1[u];
+        }
     }
 }
 
@@ -155,13 +164,23 @@ constexpr int kMaxTasks = ((kTileX / 4 + 2 * ((PF_CHAIN_HALO_MAX + 3) / 4) + 2) 
 template <int R, bool EXACT>
 __device__ __forceinline__ void tile_passes(float *buf, int pitch, const float *__restrict__ filt,
                                             float *__restrict__ out, int h, int w, int passes, int border, int x0,
-                                            int y0, bool interior) {
+                                            int y0, bool interior, int first) {
     constexpr int K = 2 * R + 1;
     constexpr int PAD = lds_pad(R);
     constexpr int NB = 1 + 2 * PAD / 4;  // 16-byte blocks per window row
     const int H = R * passes;
     const int ox = x0 - H, oy = y0 - H;
     const int cx = PAD - ox;  // buffer column of image column x is x + cx
+    // The taps, loaded once: read inside the task loop, their scalar loads
+    // would share the LDS reads' wait counter and force a full wait in the
+    // middle of every task.
+    float wk[K * K];
+#pragma unroll
+    for (int i = 0; i < K * K; ++i) wk[i] = filt[i];
+    // A pass with fewer tasks than threads leaves whole waves idle, and each
+    // wave of the workgroup runs on its own SIMD: the wave that takes the
+    // pass's first tasks (`first`) therefore moves on past the waves the
+    // previous pass used, so that the passes' work spreads over the SIMDs.
     // One LDS image: a pass computes its whole region into registers, and
     // only after a barrier overwrites the previous pass's image with it.
     for (int p = 1; p <= passes; ++p) {
@@ -175,18 +194,21 @@ __device__ __forceinline__ void tile_passes(float *buf, int pitch, const float *
         // H - m) to c + 3 + PAD < pitch, rows from ylo - R - oy >= H - m - R
         // >= 0 to at most yhi + 3 + R - oy < rows (4 spare rows). Outputs
         // outside [ylo, yhi) x [xlo, xhi) are computed from whatever the
-        // buffer holds there and never stored.
+        // buffer holds there: the last pass does not store them, and task
+        // writes back to LDS (rows up to yhi + 2 - oy, columns up to c + 3)
+        // stay inside the buffer too.
         const int cb0 = (xlo + cx) >> 2, cb1 = ((xhi - 1 + cx) >> 2) + 1;
         const int ncb = cb1 - cb0, ntask = ((yhi - ylo + 3) >> 2) * ncb;
         float res[kMaxTasks][4][4];
         int at_y[kMaxTasks], at_c[kMaxTasks];
-        Walk t(threadIdx.x, ncb);
+        const int v = (threadIdx.x - 64 * first) & (kThreads - 1);  // this thread's place in task order
+        Walk t(v, ncb);
 #pragma unroll
         for (int u = 0; u < kMaxTasks; ++u) {
             at_y[u] = ylo + 4 * t.row;
             at_c[u] = 4 * (cb0 + t.col);
             t.next();
-            if (threadIdx.x + u * kThreads >= ntask) continue;
+            if (v + u * kThreads >= ntask) continue;
             const float *base = buf + (at_y[u] - R - oy) * pitch + (at_c[u] - PAD);
             float acc[4][4];
 #pragma unroll
@@ -212,7 +234,7 @@ __device__ __forceinline__ void tile_passes(float *buf, int pitch, const float *
                     if (dy < 0 || dy >= K) continue;
 #pragma unroll
                     for (int dx = 0; dx < K; ++dx) {
-                        const float wt = filt[dy * K + dx];
+                        const float wt = wk[dy * K + dx];
 #pragma unroll
                         for (int k = 0; k < 4; ++k) acc[j][k] = madd<EXACT>(wt, v[PAD - R + k + dx], acc[j][k]);
                     }
@@ -226,7 +248,7 @@ __device__ __forceinline__ void tile_passes(float *buf, int pitch, const float *
         if (last) {
 #pragma unroll
             for (int u = 0; u < kMaxTasks; ++u) {
-                if (threadIdx.x + u * kThreads >= ntask) continue;
+                if (v + u * kThreads >= ntask) continue;
                 const int x = at_c[u] - cx;
                 const bool full = x >= xlo && x + 3 < xhi;
 #pragma unroll
@@ -252,29 +274,23 @@ __device__ __forceinline__ void tile_passes(float *buf, int pitch, const float *
             }
             break;
         }
+        first = (first + ((ntask + 63) >> 6)) & 3;
         lds_barrier();  // every read of the previous image is done
+        // Whole tasks go back to LDS, also their outputs outside the region:
+        // those positions lie inside the buffer (the bounds above), and the
+        // next pass reads none of them, except out-of-image positions, which
+        // the border extension below rewrites first.
 #pragma unroll
         for (int u = 0; u < kMaxTasks; ++u) {
-            if (threadIdx.x + u * kThreads >= ntask) continue;
-            const int x = at_c[u] - cx;
-            const bool full = x >= xlo && x + 3 < xhi;
+            if (v + u * kThreads >= ntask) continue;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int y = at_y[u] + j;
-                if (y >= yhi) continue;
-                float *o = buf + (y - oy) * pitch + at_c[u];
-                if (full) {
-                    f4 q;
-                    q.x = res[u][j][0];
-                    q.y = res[u][j][1];
-                    q.z = res[u][j][2];
-                    q.w = res[u][j][3];
-                    *reinterpret_cast<f4 *>(o) = q;
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (x + k >= xlo && x + k < xhi) o[k] = res[u][j][k];
-                }
+                f4 q;
+                q.x = res[u][j][0];
+                q.y = res[u][j][1];
+                q.z = res[u][j][2];
+                q.w = res[u][j][3];
+                *reinterpret_cast<f4 *>(buf + (at_y[u] + j - oy) * pitch + at_c[u]) = q;
             }
         }
         lds_barrier();
@@ -316,11 +332,11 @@ __global__ __launch_bounds__(kThreads) void k_chain_f32(const float *__restrict_
     const bool interior = ox >= 0 && oy >= 0 && x0 + kTileX + H <= w && y0 + kTileY + H <= h;
     // Pass 0: the input region, border-extended.
     if (interior)
-        load_region<false>(in, lds, h, w, oy, ox, rows - 4, W0, pitch, PAD - ox, border);
+        load_region<false>(in, lds, h, w, oy, ox, rows - 4, W0, pitch, PAD, border);
     else
-        load_region<true>(in, lds, h, w, oy, ox, rows - 4, W0, pitch, PAD - ox, border);
+        load_region<true>(in, lds, h, w, oy, ox, rows - 4, W0, pitch, PAD, border);
     __syncthreads();
-    tile_passes<R, EXACT>(lds, pitch, filt, out, h, w, passes, border, x0, y0, interior);
+    tile_passes<R, EXACT>(lds, pitch, filt, out, h, w, passes, border, x0, y0, interior, tile & 3);
 }
 
 template <int R, bool EXACT>
