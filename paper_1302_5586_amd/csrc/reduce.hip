@@ -110,6 +110,14 @@ __global__ __launch_bounds__(kThreads) void k_sum_final(const double *__restrict
 // histogram serialises lanes whose bins share a bank).
 constexpr int kCopies = 32;
 
+// Counts the four bytes of a word into a thread's copy of the histogram.
+__device__ __forceinline__ void count_word(uint32_t *mine, uint32_t v) {
+    atomicAdd(&mine[kCopies * (v & 0xff)], 1u);
+    atomicAdd(&mine[kCopies * ((v >> 8) & 0xff)], 1u);
+    atomicAdd(&mine[kCopies * ((v >> 16) & 0xff)], 1u);
+    atomicAdd(&mine[kCopies * (v >> 24)], 1u);
+}
+
 __global__ __launch_bounds__(kThreads) void k_hist_partial(const uint8_t *__restrict__ x, int64_t n,
                                                            uint32_t *__restrict__ sub) {
     __shared__ uint32_t hs[256 * kCopies];
@@ -121,7 +129,32 @@ __global__ __launch_bounds__(kThreads) void k_hist_partial(const uint8_t *__rest
         const int64_t base = sp * kHistSpan;
         const int64_t len = min(kHistSpan, n - base);
         const uint8_t *p = x + base;
-        if (((uintptr_t)p & 3) == 0) {
+        if (((uintptr_t)p & 15) == 0) {
+            const int64_t nv = len / 16;  // whole 16-byte groups of the span
+            const uint4 *q = reinterpret_cast<const uint4 *>(p);
+            int64_t i = threadIdx.x;
+            // Four 16-byte loads per thread in flight per step.
+            for (; i + 3 * kThreads < nv; i += 4 * kThreads) {
+                uint4 v[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v[k] = q[i + k * kThreads];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    count_word(mine, v[k].x);
+                    count_word(mine, v[k].y);
+                    count_word(mine, v[k].z);
+                    count_word(mine, v[k].w);
+                }
+            }
+            for (; i < nv; i += kThreads) {
+                const uint4 v = q[i];
+                count_word(mine, v.x);
+                count_word(mine, v.y);
+                count_word(mine, v.z);
+                count_word(mine, v.w);
+            }
+            for (int64_t j = 16 * nv + threadIdx.x; j < len; j += kThreads) atomicAdd(&mine[kCopies * p[j]], 1u);
+        } else if (((uintptr_t)p & 3) == 0) {
             const int64_t nw = len / 4;  // whole dwords of the span
             const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
             int64_t i = threadIdx.x;

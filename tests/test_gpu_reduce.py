@@ -92,6 +92,11 @@ def test_hist_constant_unaligned_and_rgb():
     assert view.data_ptr() % 4 != 0
     got = pf.hist256_u8(view).cpu().numpy()
     assert np.array_equal(got, oracle.hist256_u8(y[1:]))
+    # a start aligned to 4 bytes but not to 16 (the word path)
+    view = yt[4:]
+    assert view.data_ptr() % 16 != 0
+    got = pf.hist256_u8(view).cpu().numpy()
+    assert np.array_equal(got, oracle.hist256_u8(y[4:]))
     cfg = synth.config_rgb()
     got = pf.hist256_u8(_t(cfg.image, dev)).cpu().numpy()
     assert np.array_equal(got, oracle.hist256_u8(cfg.image.reshape(-1)))
