@@ -41,9 +41,14 @@ def tolerance_2d(img: np.ndarray, f2d: np.ndarray, r: int) -> np.ndarray:
 
 
 def tolerance_sep(img: np.ndarray, fx: np.ndarray, fy: np.ndarray) -> np.ndarray:
+    """Per-element allowed error for a separable filter: D is the separable
+    oracle over |x| with |fx| and |fy|, which equals sum |fy[a] fx[b]| |x|
+    over the window up to its own rounding (below 1e-6 relative)."""
     r = (fx.size - 1) // 2
-    f2 = np.outer(np.abs(fy).astype(np.float64), np.abs(fx).astype(np.float64)).astype(np.float32)
-    return tolerance_2d(img, f2, r)
+    d = oracle.filter_sep_f32(np.abs(img), np.abs(fx), np.abs(fy)).astype(np.float64) * (1 + 1e-6)
+    n = (2 * r + 1) ** 2
+    rel = 1e-5 if r <= 4 else 2 * gamma(n) + U
+    return rel * d + 1e-30
 
 
 def assert_close(got: np.ndarray, ref: np.ndarray, tol: np.ndarray, what: str = ""):

@@ -143,11 +143,10 @@ def test_exact_batch_matches_oracle_bitwise():
 
 
 def test_config_batch_512():
-    """The 512-image batch (seed 3): every image bit-identical to its single
-    launch; a sample of 40 images against the oracle element by element; and
-    the full batch against the oracle on sampled pixels of every image.
-    Run with the committed MI355X tune table, the launch configuration the
-    benchmark times."""
+    """The 512-image batch (seed 3), in the launch configuration the
+    benchmark times (the committed MI355X tune table, graph replay): every
+    element of every image against the separable oracle within 1e-5 * D,
+    and every image bit-identical to its single-image launch."""
     dev = device()
     import os
     import torch
@@ -165,31 +164,25 @@ def _config_batch_512(dev, torch):
     filts = [np.concatenate([b.fx[i], b.fx[i]]) for i in range(b.n)]
     pk = pf.pack_batch(b.images, filts, [pf.KIND_SEP] * b.n)
     x, fl = _t(pk.pixels, dev), _t(pk.filters, dev)
-    out = torch.empty_like(x)
+    out = torch.full_like(x, float("nan"))
     plan = pf.BatchPlan(pk.h, pk.w, pk.r, pk.kind, pk.pix_off, pk.filt_off, x.numel(), fl.numel(), graph=True)
     plan.run(x, fl, out)
     plan.run(x, fl, out)
     var = plan.variants()
     got = out.cpu().numpy()
-    rng = np.random.default_rng(0)
+    worst_abs, worst_rel = 0.0, 0.0
     for i in range(b.n):
         h, w, r = int(pk.h[i]), int(pk.w[i]), int(pk.r[i])
         gi = got[pk.pix_off[i]:pk.pix_off[i] + h * w].reshape(h, w)
+        ref, tol = _oracle_and_tol(b.images[i], filts[i], pf.KIND_SEP, r)
+        err, rel = assert_close(gi, ref, tol, "batch512 image %d (%dx%d r=%d)" % (i, h, w, r))
+        worst_abs, worst_rel = max(worst_abs, err), max(worst_rel, rel)
         xi = x[pk.pix_off[i]:pk.pix_off[i] + h * w].view(h, w)
         fi = fl[pk.filt_off[i]:pk.filt_off[i] + 2 * (2 * r + 1)]
         alone = _single(xi, fi, pf.KIND_SEP, r, int(var[i]), dev).cpu().numpy()
-        assert np.array_equal(alone, gi), i
-        if i % 13 == 0:
-            ref, tol = _oracle_and_tol(b.images[i], filts[i], pf.KIND_SEP, r)
-            assert_close(gi, ref, tol, "batch512 image %d" % i)
-        else:
-            # sampled pixels, including the four corners, against the 2D oracle
-            f2 = synth.outer_2d(b.fx[i], b.fx[i])
-            ys = np.concatenate([[0, 0, h - 1, h - 1], rng.integers(0, h, 12)])
-            xs = np.concatenate([[0, w - 1, 0, w - 1], rng.integers(0, w, 12)])
-            for y, xx in zip(ys, xs):
-                o = float(oracle.filter2d_f32_at(b.images[i], f2, r, int(y), int(xx)))
-                assert abs(float(gi[y, xx]) - o) <= 2e-5 * abs(o) + 1e-30, (i, y, xx)
+        assert np.array_equal(alone, gi), "image %d differs between batch and single launch" % i
+    print("batch512: %d images, %d px, every element checked; max abs %.3g, max rel %.3g"
+          % (b.n, b.pixels, worst_abs, worst_rel))
 
 
 def test_batch_autotune_keeps_results(tmp_path):

@@ -112,6 +112,11 @@ def test_config_large_full():
     print("4096^2 sep: max abs %.3g max rel %.3g" % (err, rel))
     # the two forms of the same Gaussian agree within both bounds
     assert_close(gots, ref2, 2 * tolerance_2d(cfg.image, cfg.f2d, 2), "4096^2 sep vs 2d")
+    # exact mode: both forms bit for bit equal to the sequential definition
+    ex2 = pf.filter2d(x, _t(cfg.f2d, dev), exact=True).cpu().numpy()
+    assert np.array_equal(ex2, ref2), "4096^2 exact 2d: %d pixels differ" % int((ex2 != ref2).sum())
+    exs = pf.filter_sep(x, g, g, exact=True).cpu().numpy()
+    assert np.array_equal(exs, refs), "4096^2 exact sep: %d pixels differ" % int((exs != refs).sum())
 
 
 @pytest.mark.parametrize("r", range(0, 9))

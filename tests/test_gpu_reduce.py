@@ -14,7 +14,8 @@ from gpu_util import device
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [1, 3, 4, 5, 1023, 16383, 16384, 16385, 65537, 3 * 65536 + 5, 1 << 20]
+# 65536 is the chunk length: one full chunk, one short of it, one past it.
+SIZES = [1, 3, 4, 5, 1023, 16383, 16384, 16385, 65535, 65536, 65537, 2 * 65536, 3 * 65536 + 5, 1 << 20]
 
 
 def _t(a, dev):
@@ -34,7 +35,7 @@ def test_sum_against_oracle(n):
     assert got[1] == got[0] / n
 
 
-@pytest.mark.parametrize("n", [1, 65537, 3 * 65536 + 5, 1 << 22])
+@pytest.mark.parametrize("n", [1, 65535, 65536, 65537, 3 * 65536 + 5, 1 << 22])
 def test_sum_integers_exact(n):
     dev = device()
     rng = np.random.default_rng(7 + n)
