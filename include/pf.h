@@ -236,9 +236,16 @@ pf_status pf_filter_f32_shaped(int32_t h, int32_t w, int32_t r, int32_t kind, in
                                int32_t flags, void *stream);
 
 /* ---- tuning (profile-based auto-tuning, Sec. II, Fig. 1 flow) -------------
- * The tune table maps (kind, r, size class) to a variant and a launch
- * shape. Size classes: 0 small (< 256*256 px), 1 medium, 2 large
- * (> 1024*1024 px). A built-in default table is used until one is loaded. */
+ * The tune table maps (context, kind, r, size class) to a variant and a
+ * launch shape. Contexts: PF_TUNE_SINGLE for single-image calls,
+ * PF_TUNE_BATCH for the persistent batch kernel of batch plans and servers
+ * (FP32 kinds only; four waves per workgroup; direct or separable
+ * variant). Size classes: 0 small (< 256*256 px), 1 medium, 2 large
+ * (> 1024*1024 px). A built-in default table is used until one is loaded.
+ * Results depend on the variant only, never on the launch shape. */
+#define PF_TUNE_SINGLE 0
+#define PF_TUNE_BATCH  1
+
 typedef struct pf_tune_entry {
     int32_t kind;             /* PF_KIND_2D, PF_KIND_SEP, PF_KIND_U8 */
     int32_t r;                /* 0..PF_R_MAX                   */
@@ -246,21 +253,30 @@ typedef struct pf_tune_entry {
     int32_t variant;          /* PF_VAR_*                      */
     int32_t rows_per_wave;
     int32_t waves_per_group;
-    float   us;               /* measured median time, or 0    */
+    float   us;               /* measured median time of the winning candidate (us), or 0:
+                                 one launch of the class image (PF_TUNE_SINGLE), one batch
+                                 launch of class images (PF_TUNE_BATCH, pf_autotune) or of
+                                 the whole tuned batch (PF_TUNE_BATCH, pf_batch_autotune) */
+    int32_t context;          /* PF_TUNE_SINGLE or PF_TUNE_BATCH */
 } pf_tune_entry;
 
-pf_status pf_tune_lookup(int32_t kind, int32_t r, int64_t pixels, PF_OUTP(pf_tune_entry, e));
+pf_status pf_tune_lookup(int32_t kind, int32_t r, int64_t pixels, int32_t context, PF_OUTP(pf_tune_entry, e));
 /* Replace the active table with n entries (missing keys keep defaults). */
 pf_status pf_tune_set(int32_t n, PF_ARR(const pf_tune_entry, entries, n));
 pf_status pf_tune_reset(void);
 /* Load / save the table as JSON text (host file path). */
 pf_status pf_tune_load(const char *path);
 pf_status pf_tune_save(const char *path);
-/* Measure every candidate for kinds {2D, SEP}, r in 0..r_max and the three
- * size classes on the current device with hipEvents (median of `reps`
- * timed runs over rotated buffers), install the winners, and write the
- * table to `path` if it is not NULL. Allocates and frees its own device
- * buffers; synchronises the device. */
+/* Measure, on the current device with hipEvents (median of `reps` timed
+ * runs over rotated buffers), for r in 0..r_max and the three size
+ * classes: every (rows_per_wave in {8, 16, 32, 64}) x (waves_per_group in
+ * {1, 2, 4, 8}) shape of single-image calls of every kind, and for
+ * PF_KIND_SEP also the PF_VAR_SEP_DIRECT variant at the best shape; and the
+ * tile heights {8, 16, 32, 64} of the batch kernel on a batch of class
+ * images (FP32 kinds). A candidate replaces the default only when at least
+ * 3% faster. Installs the winners and writes the table to `path` if it is
+ * not NULL. Allocates and frees its own device buffers; synchronises the
+ * device. */
 pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path);
 /* Workgroups (of four waves) per compute unit that persistent batch
  * launches use, a table-wide setting (saved with the table; reset to its
@@ -269,13 +285,14 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path);
  * not NULL. Fewer than fit at once is deliberate: on MI355X the fewest
  * tiles in flight ran fastest. Plans created earlier keep their grid. */
 pf_status pf_tune_batch_blocks(int32_t blocks_per_cu, int32_t *previous);
-/* Tune the table for one batch (the arguments of pf_batch_plan_create and
- * pf_batch_plan_run): for each size class present in the batch, try row
- * tiles of 8, 16, 32 and 64 for every radius and FP32 kind of that class,
- * timing whole-batch launches on the device (median of 5 x `reps`), and
- * keep a change only when the batch gets at least 3% faster. Workgroups per
- * compute unit (1..4, see pf_tune_batch_blocks) are tuned first. Installs the
- * result and writes it to `path` if not NULL. Overwrites `out`. */
+/* Tune the PF_TUNE_BATCH entries for one batch (the arguments of
+ * pf_batch_plan_create and pf_batch_plan_run): workgroups per compute unit
+ * (1..4, see pf_tune_batch_blocks) first, then for each (kind, r, size
+ * class) key the batch uses, row tiles of 8, 16, 32 and 64, timing
+ * whole-batch launches on the device (median of 5 x `reps`) and keeping a
+ * change only when the batch gets at least 3% faster. Single-image entries
+ * are not touched. Installs the result and writes it to `path` if not
+ * NULL. Overwrites `out`. */
 pf_status pf_batch_autotune(int32_t n,
                             PF_ARR(const int32_t, h, n), PF_ARR(const int32_t, w, n),
                             PF_ARR(const int32_t, r, n), PF_ARR(const int32_t, kind, n),

@@ -66,10 +66,13 @@ class PFBudget(PFError):
 _ERRORS = {PF_EINVAL: PFInvalid, PF_EALIAS: PFAlias, PF_EAGAIN: PFAgain, PF_ETIMEDOUT: PFTimeout, PF_EBUDGET: PFBudget}
 
 
+TUNE_SINGLE, TUNE_BATCH = 0, 1
+
+
 class TuneEntry(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("r", ctypes.c_int32), ("size_class", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("rows_per_wave", ctypes.c_int32),
-                ("waves_per_group", ctypes.c_int32), ("us", ctypes.c_float)]
+                ("waves_per_group", ctypes.c_int32), ("us", ctypes.c_float), ("context", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -106,7 +109,7 @@ _SIGS = {
     "pf_filter_chain_f32": (_I32, [_I32, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
     "pf_filter2d_u8": (_I32, [_I32, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
     "pf_filter_f32_shaped": (_I32, [_I32, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
-    "pf_tune_lookup": (_I32, [_I32, _I32, _I64, ctypes.POINTER(TuneEntry)]),
+    "pf_tune_lookup": (_I32, [_I32, _I32, _I64, _I32, ctypes.POINTER(TuneEntry)]),
     "pf_tune_set": (_I32, [_I32, ctypes.POINTER(TuneEntry)]),
     "pf_tune_reset": (_I32, []),
     "pf_tune_load": (_I32, [ctypes.c_char_p]),
@@ -119,6 +122,8 @@ _SIGS = {
     "pf_batch_plan_variants": (_I32, [_P, _I32, _P]),
     "pf_batch_plan_info": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "pf_batch_plan_destroy": (_I32, [_P]),
+    "pf_batch_plan_check": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _I64, _I64, _I32, ctypes.POINTER(_I64),
+                                   ctypes.POINTER(_I64)]),
     "pf_server_create": (_I32, [_I64, _I32, _I32, _I32, _I32, ctypes.POINTER(_P)]),
     "pf_server_submit": (_I32, [_P, _I32, _I32, _I32, _I32, _P, _I32, _P, _I64, ctypes.POINTER(_I64)]),
     "pf_server_poll": (_I32, [_P, _I64, ctypes.POINTER(_I32)]),
@@ -402,9 +407,11 @@ def filter_shaped(x, filt, r: int, kind: int, variant: int, rows_per_wave: int, 
 
 # ---------------------------------------------------------------- tuning
 
-def tune_lookup(kind: int, r: int, pixels: int) -> TuneEntry:
+def tune_lookup(kind: int, r: int, pixels: int, context: int = TUNE_SINGLE) -> TuneEntry:
+    """The tune entry single-image calls (TUNE_SINGLE) or batch plans and
+    servers (TUNE_BATCH) use for this key."""
     e = TuneEntry()
-    _check(load().pf_tune_lookup(kind, r, pixels, ctypes.byref(e)))
+    _check(load().pf_tune_lookup(kind, r, pixels, context, ctypes.byref(e)))
     return e
 
 
@@ -439,7 +446,7 @@ def tune_batch_blocks(blocks_per_cu: int = 0) -> int:
 
 
 def autotune_batch(h, w, r, kind, pix_off, filt_off, x, filt, out, reps: int = 10, path: str | None = None):
-    """Tune the tile heights of the table on one batch (see pf_batch_autotune)."""
+    """Tune the batch-context tile heights of the table on one batch (see pf_batch_autotune)."""
     torch = _torch()
     _dev_tensor(x, torch.float32, "x")
     _dev_tensor(filt, torch.float32, "filt")
@@ -518,6 +525,20 @@ class BatchPlan:
             self.close()
         except Exception:  # noqa: BLE001 - interpreter shutdown
             pass
+
+
+def batch_plan_check(h, w, r, kind, pix_off, filt_off, npix: int, nfilt: int, *, exact: bool = False,
+                     no_tune: bool = False) -> dict:
+    """Host-only replay of a batch plan's tile table (see pf_batch_plan_check):
+    returns {"tiles": checked, "violations": found}; raises on a violation."""
+    hh, ww, rr, kk = _i32(h), _i32(w), _i32(r), _i32(kind)
+    po, fo = _i64(pix_off), _i64(filt_off)
+    flags = (FLAG_EXACT if exact else 0) | (BATCH_NO_TUNE if no_tune else 0)
+    tiles, bad = _I64(), _I64()
+    _check(load().pf_batch_plan_check(hh.size, _np_ptr(hh), _np_ptr(ww), _np_ptr(rr), _np_ptr(kk), _np_ptr(po),
+                                      _np_ptr(fo), int(npix), int(nfilt), flags, ctypes.byref(tiles),
+                                      ctypes.byref(bad)))
+    return {"tiles": tiles.value, "violations": bad.value}
 
 
 @dataclass

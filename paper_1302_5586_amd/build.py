@@ -50,10 +50,18 @@ def _jobs():
     return out
 
 
-def _compile(job, verbose: bool, objdir: str = OBJDIR, extra=()) -> str:
+def _newest_header() -> float:
+    hs = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h"))
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(job, verbose: bool, objdir: str = OBJDIR, extra=(), incremental: bool = False) -> str:
     src, tag, defs = job
     defs = list(defs) + list(extra)
     obj = os.path.join(objdir, os.path.basename(src) + (("." + tag) if tag else "") + ".o")
+    if incremental and os.path.exists(obj) and \
+            os.path.getmtime(obj) > max(os.path.getmtime(src), _newest_header(), os.path.getmtime(__file__)):
+        return obj
     t0 = time.time()
     if src.endswith(".hip"):
         cmd = [HIPCC, "-x", "hip", *DEVICE, *COMMON, *defs, "-c", src, "-o", obj]
@@ -74,10 +82,11 @@ def _compile(job, verbose: bool, objdir: str = OBJDIR, extra=()) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 0, defines=(), out: str = LIB) -> str:
+def build(verbose: bool = False, jobs: int = 0, defines=(), out: str = LIB, incremental: bool = False) -> str:
     """Compile every source and link the shared library; returns its path.
     ``defines`` (e.g. ["-DPF_STRIP_ALIGNED=0"]) and ``out`` build a variant
-    of the library elsewhere, in its own object directory."""
+    of the library elsewhere, in its own object directory. ``incremental``
+    keeps objects newer than their source, every header and this script."""
     objdir = OBJDIR if not defines else OBJDIR + "_" + "_".join(d.lstrip("-D").replace("=", "") for d in defines)
     os.makedirs(objdir, exist_ok=True)
     work = _jobs()
@@ -85,7 +94,7 @@ def build(verbose: bool = False, jobs: int = 0, defines=(), out: str = LIB) -> s
     work.sort(key=lambda j: (not j[0].endswith(".hip"), -len(j[1])))
     jobs = jobs or min(os.cpu_count() or 8, 16, len(work))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda j: _compile(j, verbose, objdir, defines), work))
+        objs = list(ex.map(lambda j: _compile(j, verbose, objdir, defines, incremental), work))
     tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, *DEVICE, "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     if verbose:
@@ -101,4 +110,5 @@ def build(verbose: bool = False, jobs: int = 0, defines=(), out: str = LIB) -> s
 if __name__ == "__main__":
     defs = [a for a in sys.argv[1:] if a.startswith("-D")]
     outs = [a[len("--out="):] for a in sys.argv[1:] if a.startswith("--out=")]
-    print(build(verbose="-v" in sys.argv, defines=defs, out=outs[0] if outs else LIB))
+    print(build(verbose="-v" in sys.argv, defines=defs, out=outs[0] if outs else LIB,
+                incremental="--incremental" in sys.argv))

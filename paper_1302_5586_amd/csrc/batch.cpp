@@ -72,19 +72,13 @@ static hipKernelNodeParams node_params(pf_batch_plan *p, int g, BatchArgs &a) {
     return kp;
 }
 
-}  // namespace pf
-
-using namespace pf;
-
-extern "C" {
-
-pf_status pf_batch_plan_create(int32_t n, const int32_t *__restrict h, const int32_t *__restrict w,
-                               const int32_t *__restrict r, const int32_t *__restrict kind,
-                               const int64_t *__restrict pix_off, const int64_t *__restrict filt_off, int64_t npix,
-                               int64_t nfilt, int32_t flags, pf_batch_plan **const __restrict plan) {
-    clear_error();
-    if (!plan) return fail(PF_EINVAL, "null plan out-parameter");
-    *plan = nullptr;
+// Validates a batch description (sizes, radii, kinds, arena ranges, no two
+// images overlapping) and builds the plan's host tables: per radius group
+// (0..4, 5..8) the image descriptors with their variant and tile height from
+// the batch context of the tune table, and the flat list of wave tiles.
+pf_status build_plan_tables(int32_t n, const int32_t *h, const int32_t *w, const int32_t *r, const int32_t *kind,
+                            const int64_t *pix_off, const int64_t *filt_off, int64_t npix, int64_t nfilt,
+                            int32_t flags, PlanTables *t) {
     if (n < 1) return fail(PF_EINVAL, "batch needs at least one image");
     if (!h || !w || !r || !kind || !pix_off || !filt_off) return fail(PF_EINVAL, "null descriptor array");
     if (npix < 1 || nfilt < 1) return fail(PF_EINVAL, "arena sizes must be >= 1");
@@ -110,18 +104,8 @@ pf_status pf_batch_plan_create(int32_t n, const int32_t *__restrict h, const int
         if (spans[i - 1].first + spans[i - 1].second > spans[i].first)
             return fail(PF_EALIAS, "two images overlap in the pixel arena");
 
-    pf_batch_plan *p = new (std::nothrow) pf_batch_plan;
-    if (!p) return fail(PF_ENOMEM, "plan allocation");
-    p->n = n;
-    p->npix = npix;
-    p->nfilt = nfilt;
-    p->flags = flags;
-    (void)hipGetDevice(&p->device);
-    p->variant.resize(n);
-
-    std::vector<BatchImg> imgs[2];
+    t->variant.resize(n);
     int64_t ntiles[2] = {0, 0};
-    int used[2] = {0, 0};
     for (int i = 0; i < n; ++i) {
         const int64_t px = (int64_t)h[i] * w[i];
         pf_tune_entry e;
@@ -129,12 +113,12 @@ pf_status pf_batch_plan_create(int32_t n, const int32_t *__restrict h, const int
             e.variant = kind[i] == PF_KIND_SEP ? PF_VAR_SEPARABLE : PF_VAR_DIRECT;
             e.rows_per_wave = 16;
         } else {
-            e = tune_lookup(kind[i], r[i], px);
+            e = tune_lookup_batch(kind[i], r[i], px);
         }
-        int var = kind[i] == PF_KIND_2D ? PF_VAR_DIRECT : (e.variant == PF_VAR_SEP_DIRECT ? PF_VAR_SEP_DIRECT : PF_VAR_SEPARABLE);
-        p->variant[i] = var;
+        const int var = kind[i] == PF_KIND_2D ? PF_VAR_DIRECT : PF_VAR_SEPARABLE;
+        t->variant[i] = var;
         const int g = r[i] <= 4 ? 0 : 1;
-        used[g] |= 1 << var;
+        t->used[g] |= 1 << var;
         BatchImg d;
         d.in_off = pix_off[i];
         d.out_off = pix_off[i];
@@ -145,27 +129,114 @@ pf_status pf_batch_plan_create(int32_t n, const int32_t *__restrict h, const int
         d.var = var;
         d.by = e.rows_per_wave;
         const int64_t nt = set_strips(d);
-        if (ntiles[g] + nt > INT32_MAX) {
-            delete p;
-            return fail(PF_EUNSUPPORTED, "batch has more than 2^31-1 wave tiles");
-        }
+        if (ntiles[g] + nt > INT32_MAX) return fail(PF_EUNSUPPORTED, "batch has more than 2^31-1 wave tiles");
         ntiles[g] += nt;
-        imgs[g].push_back(d);
+        t->imgs[g].push_back(d);
     }
-    std::vector<BatchTask> tasks[2];
+    for (int g = 0; g < 2; ++g) {
+        t->tasks[g].reserve((size_t)ntiles[g]);
+        for (size_t i = 0; i < t->imgs[g].size(); ++i) append_tiles(t->tasks[g], (int32_t)i, t->imgs[g][i]);
+    }
+    return PF_OK;
+}
+
+// Replays, on the host, where every wave tile of the tables reads and
+// writes, with the geometry functions the FP32 strip kernel itself calls
+// (strip_mode, lane_col, vec_load_col, halo_load_col, tile_strip): each
+// tile must name a valid image and a strip and row band inside it; each
+// 16-byte load of a lane (kStripFast, kStripEdge), each halo load of an
+// aligned strip (kStripFast) and each plain 16-byte store (kStripFast
+// without halo lanes) must lie in [0, w) of its row; and the image must lie
+// inside the pixel arena. Loads of single clamped columns and stores
+// through range-checked buffer resources stay in bounds by construction.
+// Returns the number of violations; the first is described in *first.
+int64_t check_plan_tables(const PlanTables &t, int64_t npix, std::string *first) {
+    int64_t bad = 0;
+    auto report = [&](int g, size_t k, const std::string &what) {
+        if (!bad++) *first = "group " + std::to_string(g) + " tile " + std::to_string(k) + ": " + what;
+    };
+    for (int g = 0; g < 2; ++g) {
+        const std::vector<BatchImg> &imgs = t.imgs[g];
+        for (const BatchImg &d : imgs)
+            if (d.in_off < 0 || d.in_off + (int64_t)d.h * d.w > npix || d.out_off < 0 ||
+                d.out_off + (int64_t)d.h * d.w > npix) {
+                report(g, 0, "image outside the arena");
+            }
+        for (size_t k = 0; k < t.tasks[g].size(); ++k) {
+            const BatchTask tk = t.tasks[g][k];
+            if (tk.img < 0 || tk.img >= (int)imgs.size()) {
+                report(g, k, "image index out of range");
+                continue;
+            }
+            const BatchImg &d = imgs[tk.img];
+            if (tk.tile < 0 || tk.tile >= d.strips_x * d.strips_y) {
+                report(g, k, "tile number out of range");
+                continue;
+            }
+            int sx = 0, sy = 0;
+            tile_strip(kTileColMajorF32, tk.tile, d.strips_x, d.strips_y, sx, sy);
+            const int x0 = sx * strip_width(d.r), y0 = sy * d.by;
+            const int rows = std::min(d.by, d.h - y0);
+            if (x0 < 0 || x0 >= d.w || y0 < 0 || rows < 1 || y0 + rows > d.h) {
+                report(g, k, "strip origin or row band outside the image");
+                continue;
+            }
+            const int mode = strip_mode(d.r, x0, d.w);
+            for (int lane = 0; lane < 64; ++lane) {
+                const int xs = lane_col(d.r, x0, lane);
+                if (mode != kStripTiny) {
+                    const int c = vec_load_col(d.r, mode, xs, d.w);
+                    if (c < 0 || c + 4 > d.w) report(g, k, "16-byte load outside the row (lane " + std::to_string(lane) + ")");
+                }
+                if (mode == kStripFast && aligned_strip(d.r)) {
+                    const int c = halo_load_col(d.r, lane < 32, x0, d.w);
+                    if (c < 0 || c + d.r > d.w) report(g, k, "halo load outside the row (lane " + std::to_string(lane) + ")");
+                }
+                if (mode == kStripFast && idle_lanes(d.r) == 0 && (xs < 0 || xs + 4 > d.w))
+                    report(g, k, "16-byte store outside the row (lane " + std::to_string(lane) + ")");
+            }
+        }
+    }
+    return bad;
+}
+
+}  // namespace pf
+
+using namespace pf;
+
+extern "C" {
+
+pf_status pf_batch_plan_create(int32_t n, const int32_t *__restrict h, const int32_t *__restrict w,
+                               const int32_t *__restrict r, const int32_t *__restrict kind,
+                               const int64_t *__restrict pix_off, const int64_t *__restrict filt_off, int64_t npix,
+                               int64_t nfilt, int32_t flags, pf_batch_plan **const __restrict plan) {
+    clear_error();
+    if (!plan) return fail(PF_EINVAL, "null plan out-parameter");
+    *plan = nullptr;
+    PlanTables t;
+    pf_status st = build_plan_tables(n, h, w, r, kind, pix_off, filt_off, npix, nfilt, flags, &t);
+    if (st) return st;
+
+    pf_batch_plan *p = new (std::nothrow) pf_batch_plan;
+    if (!p) return fail(PF_ENOMEM, "plan allocation");
+    p->n = n;
+    p->npix = npix;
+    p->nfilt = nfilt;
+    p->flags = flags;
+    (void)hipGetDevice(&p->device);
+    p->variant = t.variant;
     size_t bytes = 0;
     size_t off_imgs[2], off_tasks[2];
     for (int g = 0; g < 2; ++g) {
-        p->ntasks[g] = ntiles[g];
-        p->mask[g] = batch_mask(g, used[g]);
-        p->grid[g] = ntiles[g] ? batch_grid(g, (flags & PF_FLAG_EXACT) != 0, p->mask[g], p->wpg, ntiles[g]) : 0;
-        tasks[g].reserve((size_t)ntiles[g]);
-        for (size_t i = 0; i < imgs[g].size(); ++i) append_tiles(tasks[g], (int32_t)i, imgs[g][i]);
+        const int64_t ntiles = (int64_t)t.tasks[g].size();
+        p->ntasks[g] = ntiles;
+        p->mask[g] = batch_mask(g, t.used[g]);
+        p->grid[g] = ntiles ? batch_grid(g, (flags & PF_FLAG_EXACT) != 0, p->mask[g], p->wpg, ntiles) : 0;
         off_imgs[g] = bytes;
-        bytes += imgs[g].size() * sizeof(BatchImg);
+        bytes += t.imgs[g].size() * sizeof(BatchImg);
         bytes = (bytes + 255) & ~(size_t)255;
         off_tasks[g] = bytes;
-        bytes += tasks[g].size() * sizeof(BatchTask);
+        bytes += t.tasks[g].size() * sizeof(BatchTask);
         bytes = (bytes + 255) & ~(size_t)255;
     }
     hipError_t e = hipMalloc(&p->dev, std::max<size_t>(bytes, 256));
@@ -175,8 +246,9 @@ pf_status pf_batch_plan_create(int32_t n, const int32_t *__restrict h, const int
     }
     std::vector<char> host(std::max<size_t>(bytes, 256), 0);
     for (int g = 0; g < 2; ++g) {
-        if (!imgs[g].empty()) memcpy(host.data() + off_imgs[g], imgs[g].data(), imgs[g].size() * sizeof(BatchImg));
-        if (!tasks[g].empty()) memcpy(host.data() + off_tasks[g], tasks[g].data(), tasks[g].size() * sizeof(BatchTask));
+        if (!t.imgs[g].empty()) memcpy(host.data() + off_imgs[g], t.imgs[g].data(), t.imgs[g].size() * sizeof(BatchImg));
+        if (!t.tasks[g].empty())
+            memcpy(host.data() + off_tasks[g], t.tasks[g].data(), t.tasks[g].size() * sizeof(BatchTask));
         p->imgs[g] = (const BatchImg *)((char *)p->dev + off_imgs[g]);
         p->tasks[g] = (const BatchTask *)((char *)p->dev + off_tasks[g]);
     }
@@ -187,6 +259,24 @@ pf_status pf_batch_plan_create(int32_t n, const int32_t *__restrict h, const int
         return fail_hip(e, "plan descriptor upload");
     }
     *plan = p;
+    return PF_OK;
+}
+
+pf_status pf_batch_plan_check(int32_t n, const int32_t *__restrict h, const int32_t *__restrict w,
+                              const int32_t *__restrict r, const int32_t *__restrict kind,
+                              const int64_t *__restrict pix_off, const int64_t *__restrict filt_off, int64_t npix,
+                              int64_t nfilt, int32_t flags, int64_t *const __restrict tiles,
+                              int64_t *const __restrict violations) {
+    clear_error();
+    if (!tiles || !violations) return fail(PF_EINVAL, "null out-parameter");
+    *tiles = *violations = 0;
+    PlanTables t;
+    pf_status st = build_plan_tables(n, h, w, r, kind, pix_off, filt_off, npix, nfilt, flags, &t);
+    if (st) return st;
+    std::string first;
+    *tiles = (int64_t)(t.tasks[0].size() + t.tasks[1].size());
+    *violations = check_plan_tables(t, npix, &first);
+    if (*violations) return fail(PF_EINVAL, first);
     return PF_OK;
 }
 

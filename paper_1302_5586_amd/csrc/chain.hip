@@ -22,6 +22,7 @@
 // ascending), one FMA per tap, or with EXACT a separate FP32 multiply and
 // add (built with -ffp-contract=off), which reproduces the sequential
 // program bit for bit at every pass.
+#include "dev_common.h"
 #include "pf_internal.h"
 
 namespace pf {
@@ -66,11 +67,6 @@ __device__ __forceinline__ float madd(float wgt, float x, float acc) {
     }
 }
 
-__device__ __forceinline__ int xcd_remap(int b, int g) {
-    const int xcd = b & 7, idx = b >> 3;
-    const int per = g >> 3, rem = g & 7;
-    return xcd * per + min(xcd, rem) + idx;
-}
 
 // LDS layout: one image of (kTileY + 2H) rows and `pitch` floats per row.
 // Image column ox (= x0 - H) sits at buffer column pad(R), a multiple of 4

@@ -40,11 +40,12 @@
 //    every wave exits on its own.
 //
 // Workgroup ids are remapped so that consecutive tiles land on the same
-// XCD (workgroups are dealt round-robin over the 8 XCDs).
+// XCD (xcd_remap).
 #pragma once
 
 #include <type_traits>
 
+#include "dev_common.h"
 #include "pf_internal.h"
 
 namespace pf {
@@ -131,14 +132,6 @@ __device__ __forceinline__ int from_right_i(int v) {
     return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs; give the
-// workgroups that share an XCD consecutive logical ids.
-__device__ __forceinline__ int xcd_remap(int b, int g) {
-    const int xcd = b & 7, idx = b >> 3;
-    const int per = g >> 3, rem = g & 7;
-    return xcd * per + min(xcd, rem) + idx;
-}
-
 template <bool EXACT>
 __device__ __forceinline__ float madd(float wgt, float x, float acc) {
     if constexpr (EXACT) {
@@ -183,15 +176,8 @@ __device__ __forceinline__ void loadn(const float *__restrict__ p, float (&o)[N]
     }
 }
 
-// How a strip loads its rows (chosen per strip, uniform over the wave):
-//   kFast: every lane's 4 columns lie inside the image (a halo lane left of
-//          column 0 aside): one 16-byte load per lane;
-//   kEdge: some columns lie outside; the lane loads the 4 in-bounds columns
-//          nearest to its own (w >= 4) and picks each clamped column from
-//          them;
-//   kTiny: images narrower than 4 columns: one clamped load per column.
-// All three are branch-free.
-constexpr int kFast = 0, kEdge = 1, kTiny = 2;
+// Load modes of a strip (strip_mode); all three are branch-free.
+constexpr int kFast = kStripFast, kEdge = kStripEdge, kTiny = kStripTiny;
 
 __device__ __forceinline__ float pick4(const f4u &t, int i) {
     return i == 0 ? t.x : (i == 1 ? t.y : (i == 2 ? t.z : t.w));
@@ -206,21 +192,21 @@ __device__ __forceinline__ void load_row(const float *__restrict__ row, int xs, 
     if constexpr (MODE == kFast) {
         if constexpr (idle_lanes(R) > 0) {
             // The left halo lane of the first strip sits left of column 0.
-            const f4u t = ld(reinterpret_cast<const f4u *>(row + max(xs, 0)));
+            const f4u t = ld(reinterpret_cast<const f4u *>(row + vec_load_col(R, kFast, xs, w)));
             const bool left_of_image = xs < 0;
             q.v[0] = t.x;
             q.v[1] = left_of_image ? t.x : t.y;
             q.v[2] = left_of_image ? t.x : t.z;
             q.v[3] = left_of_image ? t.x : t.w;
         } else {
-            const f4u t = ld(reinterpret_cast<const f4u *>(row + xs));
+            const f4u t = ld(reinterpret_cast<const f4u *>(row + vec_load_col(R, kFast, xs, w)));
             q.v[0] = t.x;
             q.v[1] = t.y;
             q.v[2] = t.z;
             q.v[3] = t.w;
         }
     } else if constexpr (MODE == kEdge) {
-        const int xa = clampi(xs, 0, w - 4);
+        const int xa = vec_load_col(R, kEdge, xs, w);
         const f4u t = ld(reinterpret_cast<const f4u *>(row + xa));
 #pragma unroll
         for (int k = 0; k < 4; ++k) q.v[k] = pick4(t, clampi(xs + k, 0, w - 1) - xa);
@@ -231,7 +217,7 @@ __device__ __forceinline__ void load_row(const float *__restrict__ row, int xs, 
     if constexpr (aligned_strip(R)) {
         const bool left = lane < kLanes / 2;
         if constexpr (MODE == kFast) {
-            const int xh = left ? max(x0 - R, 0) : min(x0 + 4 * kLanes, w - R);
+            const int xh = halo_load_col(R, left, x0, w);
             loadn<R>(row + xh, q.hv);
             const bool edge = left ? (x0 == 0) : (x0 + 4 * kLanes == w);
             const float e = left ? q.v[0] : q.v[3];
@@ -243,16 +229,6 @@ __device__ __forceinline__ void load_row(const float *__restrict__ row, int xs, 
             for (int j = 0; j < R; ++j) q.hv[j] = row[clampi(xh + j, 0, w - 1)];
         }
     }
-}
-
-// kFast needs every lane's columns to end inside the image; for an aligned
-// strip also the R columns to its right inside it, or none.
-template <int R>
-__device__ __forceinline__ bool fast_strip(int x0, int w) {
-    constexpr int IL = idle_lanes(R);
-    const int end = x0 + 4 * (kLanes - IL);
-    if constexpr (aligned_strip(R)) return end <= w && (end == w || end + R <= w);
-    return end <= w;
 }
 
 template <int R, int VAR>
@@ -523,7 +499,7 @@ __device__ __forceinline__ void strip_f32(const float *__restrict__ in, const fl
     constexpr int K = 2 * R + 1;
     constexpr int IL = idle_lanes(R);
     const Weights<R, VAR> wt(fa, fb);
-    const int xs = x0 + 4 * (lane - IL);
+    const int xs = lane_col(R, x0, lane);
     const bool out_lane = (lane >= IL) && (lane < kLanes - IL) && (xs < w);
     float acc[K][4];
 #pragma unroll
@@ -538,9 +514,10 @@ __device__ __forceinline__ void strip_f32(const float *__restrict__ in, const fl
         for (int i0 = 0; i0 < nin; i0 += K)
             rows_group_f32<R, VAR, EXACT, 0, kTiny>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, i0, nin, out_lane);
     } else {
-        if (fast_strip<R>(x0, w)) {
+        const int mode = strip_mode(R, x0, w);
+        if (mode == kFast) {
             rows_pipelined_f32<R, VAR, EXACT, kFast, CHUNK>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, out_lane);
-        } else if (w >= 4) {
+        } else if (mode == kEdge) {
             rows_pipelined_f32<R, VAR, EXACT, kEdge, CHUNK>(wt, in, out, acc, h, w, xs, x0, lane, y0, rows, out_lane);
         } else {
             const int nin = rows + 2 * R;
@@ -558,21 +535,12 @@ __device__ __forceinline__ void strip_f32(const float *__restrict__ in, const fl
 // taken strip by strip down the image.
 // The uint8 kernel keeps column-major order (strip by strip), which
 // measured faster for it.
-#ifndef PF_TILE_COLMAJOR
-#define PF_TILE_COLMAJOR 0
-#endif
 #ifndef PF_U8_COLMAJOR
 #define PF_U8_COLMAJOR 1
 #endif
-template <bool COLMAJOR = PF_TILE_COLMAJOR != 0>
+template <bool COLMAJOR = kTileColMajorF32>
 __device__ __forceinline__ void tile_xy(int t, int strips_x, int strips_y, int &sx, int &sy) {
-    if constexpr (COLMAJOR) {
-        sx = t / strips_y;
-        sy = t - sx * strips_y;
-    } else {
-        sy = t / strips_x;
-        sx = t - sy * strips_x;
-    }
+    tile_strip(COLMAJOR, t, strips_x, strips_y, sx, sy);
 }
 
 // Single-image kernel: one wave tile per task.

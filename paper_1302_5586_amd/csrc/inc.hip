@@ -17,6 +17,7 @@
 
 #include <vector>
 
+#include "dev_common.h"
 #include "pf_internal.h"
 
 struct pf_inc_plan {
@@ -31,11 +32,6 @@ namespace inc {
 
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ int xcd_remap(int b, int g) {
-    const int xcd = b & 7, idx = b >> 3;
-    const int per = g >> 3, rem = g & 7;
-    return xcd * per + min(xcd, rem) + idx;
-}
 
 // cell[c] += edge[idx[k]] for k in off[c] .. off[c+1], in that order.
 __global__ __launch_bounds__(kThreads) void k_gather(const int32_t *__restrict__ off, const int32_t *__restrict__ idx,

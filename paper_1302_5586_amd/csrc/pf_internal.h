@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "pf.h"
+#include "pf_check.h"
 
 namespace pf {
 
@@ -28,6 +29,68 @@ constexpr int idle_lanes(int r) { return aligned_strip(r) ? 0 : halo_lanes(r); }
 constexpr int strip_width(int r) { return 4 * (64 - 2 * idle_lanes(r)); }
 // The uint8 strip keeps its halo lanes at every radius.
 constexpr int strip_width_u8(int r) { return 4 * (64 - 2 * halo_lanes(r)); }
+
+// ---- strip geometry, shared by the FP32 strip kernels and the host-side
+// check of batch plans (constexpr functions compile for host and device).
+
+// How a strip loads its rows (uniform over the wave):
+//   kStripFast: every lane's 4 columns lie inside the image (a halo lane
+//               left of column 0 aside): one 16-byte load per lane;
+//   kStripEdge: some columns lie outside; the lane loads the 4 in-bounds
+//               columns nearest to its own (w >= 4) and picks each clamped
+//               column from them;
+//   kStripTiny: one clamped load per column (images narrower than 4
+//               columns, and every strip of radii above 4).
+constexpr int kStripFast = 0, kStripEdge = 1, kStripTiny = 2;
+
+constexpr int clamp_int(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// First column of lane `lane` in a strip starting at column x0.
+constexpr int lane_col(int r, int x0, int lane) { return x0 + 4 * (lane - idle_lanes(r)); }
+
+// kStripFast needs every lane's columns to end inside the image; for an
+// aligned strip also the r columns to its right inside it, or none.
+constexpr bool fast_strip(int r, int x0, int w) {
+    const int end = x0 + 4 * (64 - idle_lanes(r));
+    return aligned_strip(r) ? (end <= w && (end == w || end + r <= w)) : end <= w;
+}
+
+constexpr int strip_mode(int r, int x0, int w) {
+    return r > 4 ? kStripTiny : (fast_strip(r, x0, w) ? kStripFast : (w >= 4 ? kStripEdge : kStripTiny));
+}
+
+// First of the 4 columns the 16-byte load of a lane with first column xs
+// reads in kStripFast and kStripEdge (a halo lane left of column 0 reads
+// columns 0..3).
+constexpr int vec_load_col(int r, int mode, int xs, int w) {
+    return mode == kStripFast ? (idle_lanes(r) > 0 ? (xs > 0 ? xs : 0) : xs) : clamp_int(xs, 0, w - 4);
+}
+
+// First of the r columns the halo load of an aligned strip reads in
+// kStripFast: left of the strip (lanes 0..31) or right of it (lanes 32..63),
+// moved inside the image at its edges.
+constexpr int halo_load_col(int r, bool left, int x0, int w) {
+    return left ? (x0 - r > 0 ? x0 - r : 0) : (x0 + 4 * 64 < w - r ? x0 + 4 * 64 : w - r);
+}
+
+// Order of the FP32 kernels' wave tiles inside an image: row-major over the
+// image's strips (0) or column-major (1).
+#ifndef PF_TILE_COLMAJOR
+#define PF_TILE_COLMAJOR 0
+#endif
+constexpr bool kTileColMajorF32 = PF_TILE_COLMAJOR != 0;
+
+// Tile number -> (strip x, strip y): row-major over the image's strips, or
+// column-major (strip by strip down the image).
+constexpr void tile_strip(bool colmajor, int t, int strips_x, int strips_y, int &sx, int &sy) {
+    if (colmajor) {
+        sx = t / strips_y;
+        sy = t - sx * strips_y;
+    } else {
+        sy = t / strips_x;
+        sx = t - sy * strips_x;
+    }
+}
 
 // One image of a batch as the persistent kernel sees it. `var` is the
 // executed variant (PF_VAR_*), `by` rows per wave tile; the image's wave
@@ -63,6 +126,20 @@ inline void append_tiles(std::vector<BatchTask> &list, int32_t img, const BatchI
     const int32_t n = d.strips_x * d.strips_y;
     for (int32_t t = 0; t < n; ++t) list.push_back({img, t});
 }
+
+// Host tables of a batch plan (batch.cpp): per radius group (0: r 0..4,
+// 1: r 5..8) the image descriptors and the flat wave-tile list, the variant
+// of each image, and the variant set each group uses.
+struct PlanTables {
+    std::vector<BatchImg> imgs[2];
+    std::vector<BatchTask> tasks[2];
+    std::vector<int32_t> variant;
+    int used[2] = {0, 0};
+};
+pf_status build_plan_tables(int32_t n, const int32_t *h, const int32_t *w, const int32_t *r, const int32_t *kind,
+                            const int64_t *pix_off, const int64_t *filt_off, int64_t npix, int64_t nfilt,
+                            int32_t flags, PlanTables *t);
+int64_t check_plan_tables(const PlanTables &t, int64_t npix, std::string *first);
 
 // Workgroups of a batch launch over `ntiles` wave tiles: `blocks_per_cu`
 // per compute unit (from the tune table), at most what fits at once, at
@@ -166,8 +243,10 @@ inline int batch_mask(int group, int used) {
     return 3;
 }
 
-// Tune table lookup (tune.cpp).
+// Tune table lookups (tune.cpp): single-image calls, and the persistent
+// batch kernel of plans and servers.
 pf_tune_entry tune_lookup(int kind, int r, int64_t pixels);
+pf_tune_entry tune_lookup_batch(int kind, int r, int64_t pixels);
 // Workgroups per compute unit of persistent batch launches (tune.cpp).
 int tune_batch_blocks_per_cu();
 

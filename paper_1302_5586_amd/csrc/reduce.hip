@@ -19,6 +19,7 @@
 // Both run as two launches over a caller-provided workspace (chunk partials,
 // per-block sub-histograms), so nothing is allocated and nothing needs
 // zeroing.
+#include "dev_common.h"
 #include "pf_internal.h"
 
 namespace pf {
@@ -32,11 +33,6 @@ constexpr int64_t kHistSpan = 1 << 18;  // bytes per histogram block task
 
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 
-__device__ __forceinline__ int xcd_remap(int b, int g) {
-    const int xcd = b & 7, idx = b >> 3;
-    const int per = g >> 3, rem = g & 7;
-    return xcd * per + min(xcd, rem) + idx;
-}
 
 // Fixed pairwise tree over the block's 256 values in LDS; returns the total
 // in thread 0.

@@ -375,7 +375,7 @@ pf_status make_request(pf_server *s, int32_t h, int32_t w, int32_t r, int32_t ki
     const int k = 2 * r + 1;
     const int nf = kind == PF_KIND_2D ? k * k : 2 * k;
     q->filt.assign(filt, filt + nf);
-    const pf_tune_entry e = tune_lookup(kind, r, (int64_t)h * w);
+    const pf_tune_entry e = tune_lookup_batch(kind, r, (int64_t)h * w);
     q->var = kind == PF_KIND_2D ? PF_VAR_DIRECT : (e.variant == PF_VAR_SEP_DIRECT ? PF_VAR_SEP_DIRECT : PF_VAR_SEPARABLE);
     q->by = e.rows_per_wave;
     if (in_is_host)

@@ -2,15 +2,20 @@
 // the variant a separable filter runs as (the paper's compilation flow ends
 // in "profile-based iterative compilation and auto-tuning", Sec. II, Fig. 1).
 //
-// The table is keyed by (kind, radius, size class) and is consulted by the
-// single-image calls, batch plans and the server. Results never depend on
-// the launch shape (each output's arithmetic is fixed), only on the
-// variant, and the variant depends only on the key.
+// The table is keyed by (context, kind, radius, size class). Context 0
+// holds the shapes of single-image calls, context 1 those of the persistent
+// batch kernel (batch plans and servers): the two launch differently (one
+// image and many small waves against a fixed grid walking many images), so
+// they are tuned and stored apart and neither tuner touches the other's
+// entries. Results never depend on the launch shape (each output's
+// arithmetic is fixed), only on the variant, and the variant depends only
+// on the key.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -23,6 +28,8 @@ namespace {
 
 constexpr int kKinds = 3;  // PF_KIND_2D, PF_KIND_SEP, PF_KIND_U8
 constexpr int kSizes = 3;
+constexpr int kContexts = 2;  // PF_TUNE_SINGLE, PF_TUNE_BATCH
+constexpr int kBatchWaves = 4;  // waves per workgroup of persistent batch launches
 
 // Workgroups per compute unit of a persistent batch launch. One (four
 // waves, one per SIMD) measured best on MI355X: the fewest tiles in flight
@@ -31,29 +38,31 @@ constexpr int kBatchBlocksPerCu = 1;
 constexpr int kBatchBlocksPerCuMax = 8;
 
 struct Table {
-    pf_tune_entry e[kKinds][PF_R_MAX + 1][kSizes];
+    pf_tune_entry e[kContexts][kKinds][PF_R_MAX + 1][kSizes];
     int batch_blocks_per_cu = kBatchBlocksPerCu;
 };
 
-pf_tune_entry default_entry(int kind, int r, int sc) {
+pf_tune_entry default_entry(int ctx, int kind, int r, int sc) {
     pf_tune_entry e;
     e.kind = kind;
     e.r = r;
     e.size_class = sc;
+    e.context = ctx;
     e.variant = (kind == PF_KIND_SEP) ? PF_VAR_SEPARABLE : PF_VAR_DIRECT;
-    // Defaults measured on MI355X: 16-row tiles for small images (and for
-    // the uint8 path), 32-row tiles otherwise.
-    e.rows_per_wave = (sc == 0 || kind == PF_KIND_U8) ? 16 : 32;
-    e.waves_per_group = kind == PF_KIND_U8 ? 1 : 4;
+    // Defaults measured on MI355X: 16-row tiles for small images, for
+    // batches and for the uint8 path, 32-row tiles otherwise.
+    e.rows_per_wave = (ctx == PF_TUNE_BATCH || sc == 0 || kind == PF_KIND_U8) ? 16 : 32;
+    e.waves_per_group = ctx == PF_TUNE_BATCH ? kBatchWaves : (kind == PF_KIND_U8 ? 1 : 4);
     e.us = 0.0f;
     return e;
 }
 
 Table make_default() {
     Table t;
-    for (int k = 0; k < kKinds; ++k)
-        for (int r = 0; r <= PF_R_MAX; ++r)
-            for (int s = 0; s < kSizes; ++s) t.e[k][r][s] = default_entry(k, r, s);
+    for (int c = 0; c < kContexts; ++c)
+        for (int k = 0; k < kKinds; ++k)
+            for (int r = 0; r <= PF_R_MAX; ++r)
+                for (int s = 0; s < kSizes; ++s) t.e[c][k][r][s] = default_entry(c, k, r, s);
     return t;
 }
 
@@ -61,13 +70,18 @@ std::mutex g_mu;
 Table g_table = make_default();
 
 bool entry_ok(const pf_tune_entry &e) {
+    if (e.context < 0 || e.context >= kContexts) return false;
     if (e.kind < 0 || e.kind >= kKinds || e.r < 0 || e.r > PF_R_MAX || e.size_class < 0 || e.size_class >= kSizes)
         return false;
     if (!valid_shape(e.rows_per_wave, e.waves_per_group)) return false;
-    // A separable filter runs separable: the persistent batch kernel
-    // compiles only the direct and separable bodies, and the table must give
-    // single-image calls and batches the same variant for the same key.
-    if (e.kind == PF_KIND_SEP) return e.variant == PF_VAR_SEPARABLE;
+    if (e.context == PF_TUNE_BATCH) {
+        // Batches hold FP32 images only; their kernel runs four waves per
+        // workgroup and compiles only the direct and separable bodies.
+        if (e.kind == PF_KIND_U8 || e.waves_per_group != kBatchWaves) return false;
+        return e.variant == (e.kind == PF_KIND_SEP ? PF_VAR_SEPARABLE : PF_VAR_DIRECT);
+    }
+    // A separable filter called alone may also run as 2D taps fy[i] * fx[j].
+    if (e.kind == PF_KIND_SEP) return e.variant == PF_VAR_SEPARABLE || e.variant == PF_VAR_SEP_DIRECT;
     return e.variant == PF_VAR_DIRECT;
 }
 
@@ -90,7 +104,12 @@ bool parse_number(const std::string &obj, const char *key, double *out) {
 
 pf_tune_entry tune_lookup(int kind, int r, int64_t pixels) {
     std::lock_guard<std::mutex> lk(g_mu);
-    return g_table.e[kind][r][size_class(pixels)];
+    return g_table.e[PF_TUNE_SINGLE][kind][r][size_class(pixels)];
+}
+
+pf_tune_entry tune_lookup_batch(int kind, int r, int64_t pixels) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_table.e[PF_TUNE_BATCH][kind][r][size_class(pixels)];
 }
 
 int tune_batch_blocks_per_cu() {
@@ -142,14 +161,13 @@ pf_status time_launch(F &&launch, int nbuf, int reps, int trials, hipStream_t s,
     return PF_OK;
 }
 
-// Representative image of each size class, and how many of them one
-// timed batch holds. Small and medium images are timed the way they run in
-// practice, many at once in the persistent batch kernel; large ones as
-// single launches.
+// Representative image of each size class, and how many of them one timed
+// batch launch holds (context 1 entries are timed on such a batch, context
+// 0 entries on single launches of one image).
 void class_shape(int sc, int kind, int *h, int *w, int *n) {
     static const int hs[kSizes] = {160, 600, 4096};
     static const int ws[kSizes] = {200, 700, 4096};
-    static const int ns[kSizes] = {1024, 96, 1};
+    static const int ns[kSizes] = {1024, 96, 4};
     *h = hs[sc];
     *w = ws[sc];
     *n = ns[sc];
@@ -214,11 +232,14 @@ using namespace pf;
 
 extern "C" {
 
-pf_status pf_tune_lookup(int32_t kind, int32_t r, int64_t pixels, pf_tune_entry *const __restrict e) {
+pf_status pf_tune_lookup(int32_t kind, int32_t r, int64_t pixels, int32_t context, pf_tune_entry *const __restrict e) {
     clear_error();
     if (!e) return fail(PF_EINVAL, "null output");
     if (kind < 0 || kind >= kKinds || r < 0 || r > PF_R_MAX || pixels < 1) return fail(PF_EINVAL, "bad tune key");
-    *e = tune_lookup(kind, r, pixels);
+    if (context != PF_TUNE_SINGLE && !(context == PF_TUNE_BATCH && kind != PF_KIND_U8))
+        return fail(PF_EINVAL, "bad tune context");
+    std::lock_guard<std::mutex> lk(g_mu);
+    *e = g_table.e[context][kind][r][size_class(pixels)];
     return PF_OK;
 }
 
@@ -230,7 +251,7 @@ pf_status pf_tune_set(int32_t n, const pf_tune_entry *__restrict entries) {
     Table t = make_default();
     for (int i = 0; i < n; ++i) {
         const pf_tune_entry &e = entries[i];
-        t.e[e.kind][e.r][e.size_class] = e;
+        t.e[e.context][e.kind][e.r][e.size_class] = e;
     }
     std::lock_guard<std::mutex> lk(g_mu);
     g_table = t;
@@ -258,16 +279,20 @@ pf_status pf_tune_save(const char *path) {
     fprintf(f, "{\n  \"library\": \"%s\",\n  \"device_arch\": \"%s\",\n  \"batch_blocks_per_cu\": %d,\n  \"entries\": [\n",
             pf_version(), d.arch.c_str(), t.batch_blocks_per_cu);
     bool first = true;
-    for (int k = 0; k < kKinds; ++k)
-        for (int r = 0; r <= PF_R_MAX; ++r)
-            for (int s = 0; s < kSizes; ++s) {
-                const pf_tune_entry &e = t.e[k][r][s];
-                fprintf(f, "%s    {\"kind\": %d, \"r\": %d, \"size_class\": %d, \"variant\": %d, \"rows_per_wave\": %d, "
-                           "\"waves_per_group\": %d, \"us\": %.3f}",
-                        first ? "" : ",\n", e.kind, e.r, e.size_class, e.variant, e.rows_per_wave, e.waves_per_group,
-                        (double)e.us);
-                first = false;
-            }
+    for (int c = 0; c < kContexts; ++c)
+        for (int k = 0; k < kKinds; ++k) {
+            if (c == PF_TUNE_BATCH && k == PF_KIND_U8) continue;
+            for (int r = 0; r <= PF_R_MAX; ++r)
+                for (int s = 0; s < kSizes; ++s) {
+                    const pf_tune_entry &e = t.e[c][k][r][s];
+                    fprintf(f,
+                            "%s    {\"context\": %d, \"kind\": %d, \"r\": %d, \"size_class\": %d, \"variant\": %d, "
+                            "\"rows_per_wave\": %d, \"waves_per_group\": %d, \"us\": %.3f}",
+                            first ? "" : ",\n", e.context, e.kind, e.r, e.size_class, e.variant, e.rows_per_wave,
+                            e.waves_per_group, (double)e.us);
+                    first = false;
+                }
+        }
     fprintf(f, "\n  ]\n}\n");
     const bool ok = fclose(f) == 0;
     return ok ? PF_OK : fail(PF_EINVAL, std::string("cannot write ") + path);
@@ -294,12 +319,13 @@ pf_status pf_tune_load(const char *path) {
         const size_t b = text.find('}', a);
         if (b == std::string::npos) return fail(PF_EINVAL, "unterminated entry in tune file");
         const std::string obj = text.substr(a, b - a + 1);
-        double v[7];
-        const char *keys[7] = {"kind", "r", "size_class", "variant", "rows_per_wave", "waves_per_group", "us"};
-        for (int i = 0; i < 7; ++i)
+        double v[8];
+        const char *keys[8] = {"kind", "r", "size_class", "variant", "rows_per_wave", "waves_per_group", "us",
+                               "context"};
+        for (int i = 0; i < 8; ++i)
             if (!parse_number(obj, keys[i], &v[i])) {
-                if (i == 6) {
-                    v[6] = 0.0;
+                if (i >= 6) {
+                    v[i] = 0.0;  // optional: measured time, context (0: single-image calls)
                 } else {
                     return fail(PF_EINVAL, std::string("tune entry without ") + keys[i]);
                 }
@@ -312,6 +338,7 @@ pf_status pf_tune_load(const char *path) {
         e.rows_per_wave = (int)v[4];
         e.waves_per_group = (int)v[5];
         e.us = (float)v[6];
+        e.context = (int)v[7];
         es.push_back(e);
         p = b + 1;
     }
@@ -377,60 +404,82 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
         if (he == hipSuccess) he = hipMemcpy(filt, taps.data(), 4096, hipMemcpyHostToDevice);
         if (he != hipSuccess) st = fail_hip(he, "autotune data upload");
     }
+    // A candidate replaces the best so far only when at least 3% faster, so
+    // timing noise does not move the table off its defaults.
+    auto better = [](float us, const pf_tune_entry &best) { return best.us == INFINITY || us < 0.97f * best.us; };
     for (int sc = 0; sc < kSizes && st == PF_OK; ++sc) {
         for (int kind = 0; kind < kKinds && st == PF_OK; ++kind) {
             int h, w, n;
             class_shape(sc, kind, &h, &w, &n);
             const size_t px = (size_t)h * w;
+            const size_t planes = kind == PF_KIND_U8 ? 3 : 1;
+            // rotating buffer sets of one image (uint8: 3 planes)
+            const int nb1 = (int)std::max<size_t>(1, std::min<size_t>(64, (big * 4 * nrot) / (px * planes * 4)));
             for (int r = 0; r <= r_max && st == PF_OK; ++r) {
-                const pf_tune_entry dflt = default_entry(kind, r, sc);
+                // ---- single-image calls: every (rows, waves) shape
+                const pf_tune_entry dflt = default_entry(PF_TUNE_SINGLE, kind, r, sc);
                 pf_tune_entry best = dflt;
                 best.us = INFINITY;
                 const int var = kind == PF_KIND_SEP ? PF_VAR_SEPARABLE : PF_VAR_DIRECT;
-                // The default shape is timed first; another shape replaces
-                // it only when at least 3% faster, so timing noise does not
-                // move the table.
                 std::vector<std::pair<int, int>> shapes;
                 shapes.push_back({dflt.rows_per_wave, dflt.waves_per_group});
                 for (int by : bys)
                     for (int wpg : wpgs)
                         if (by != dflt.rows_per_wave || wpg != dflt.waves_per_group) shapes.push_back({by, wpg});
+                auto time_single = [&](int v, int by, int wpg, float *us) -> pf_status {
+                    if (kind == PF_KIND_U8) {
+                        return time_launch(
+                            [&](int i) {
+                                const size_t o = (size_t)i * px * planes;
+                                return launch_u8(r, (const uint8_t *)in + o, (const int8_t *)filt, (uint8_t *)outb + o,
+                                                 3, h, w, 6, by, wpg, s);
+                            },
+                            nb1, reps, 3, s, us);
+                    }
+                    return time_launch(
+                        [&](int i) {
+                            const size_t o = (size_t)i * px;
+                            return launch_f32(r, v, false, in + o, filt, filt + (2 * r + 1), outb + o, h, w, by, wpg,
+                                              s);
+                        },
+                        nb1, reps, 3, s, us);
+                };
                 for (const auto &shape : shapes) {
-                    const int by = shape.first, wpg = shape.second;
-                    {
-                        if (st != PF_OK) break;
-                        float us = 0.0f;
-                        if (kind == PF_KIND_U8) {
-                            // uint8: 3 planes of the class shape
-                            const size_t plane3 = 3 * px;
-                            const int nb8 = (int)std::min<size_t>(nrot * 4, (big * 4 * nrot) / plane3);
-                            st = time_launch(
-                                [&](int i) {
-                                    return launch_u8(r, (const uint8_t *)in + (size_t)i * plane3, (const int8_t *)filt,
-                                                     (uint8_t *)outb + (size_t)i * plane3, 3, h, w, 6, by, wpg, s);
-                                },
-                                std::max(nb8, 1), reps, 3, s, &us);
-                        } else if (n > 1) {
-                            // batch kernels use 4 waves per group; time each tile height once
-                            if (wpg != 4 && !(by == dflt.rows_per_wave && wpg == dflt.waves_per_group)) continue;
-                            st = time_batch_class(kind, r, h, w, n, by, in, outb, filt, reps, s, &us);
-                        } else {
-                            st = time_launch(
-                                [&](int i) {
-                                    return launch_f32(r, var, false, in + (size_t)i * px, filt, filt + (2 * r + 1),
-                                                      outb + (size_t)i * px, h, w, by, wpg, s);
-                                },
-                                nrot, reps, 3, s, &us);
-                        }
-                        if (st == PF_OK && (best.us == INFINITY || us < 0.97f * best.us)) {
-                            best.variant = var;
-                            best.rows_per_wave = by;
-                            best.waves_per_group = wpg;
-                            best.us = us;
-                        }
+                    float us = 0.0f;
+                    st = time_single(var, shape.first, shape.second, &us);
+                    if (st != PF_OK) break;
+                    if (better(us, best)) {
+                        best.variant = var;
+                        best.rows_per_wave = shape.first;
+                        best.waves_per_group = shape.second;
+                        best.us = us;
                     }
                 }
+                // The variant axis: a separable filter may run as 2D taps.
+                if (st == PF_OK && kind == PF_KIND_SEP) {
+                    float us = 0.0f;
+                    st = time_single(PF_VAR_SEP_DIRECT, best.rows_per_wave, best.waves_per_group, &us);
+                    if (st == PF_OK && better(us, best)) {
+                        best.variant = PF_VAR_SEP_DIRECT;
+                        best.us = us;
+                    }
+                }
+                if (st != PF_OK) break;
                 out.push_back(best);
+                // ---- batch kernel: tile heights, on a batch of n class images
+                if (kind == PF_KIND_U8) continue;
+                pf_tune_entry bb = default_entry(PF_TUNE_BATCH, kind, r, sc);
+                bb.us = INFINITY;
+                for (int by : {bb.rows_per_wave, 8, 32, 64}) {
+                    float us = 0.0f;
+                    st = time_batch_class(kind, r, h, w, n, by, in, outb, filt, reps, s, &us);
+                    if (st != PF_OK) break;
+                    if (better(us, bb)) {
+                        bb.rows_per_wave = by;
+                        bb.us = us;
+                    }
+                }
+                if (st == PF_OK) out.push_back(bb);
             }
         }
     }
@@ -440,10 +489,10 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
     if (filt) (void)hipFree(filt);
     (void)hipStreamDestroy(s);
     if (st != PF_OK) return st;
-    // Keys not measured (r > r_max) keep their defaults.
+    // Keys not measured (r > r_max) keep what they had.
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        for (const pf_tune_entry &e : out) g_table.e[e.kind][e.r][e.size_class] = e;
+        for (const pf_tune_entry &e : out) g_table.e[e.context][e.kind][e.r][e.size_class] = e;
     }
     if (path) return pf_tune_save(path);
     return PF_OK;
@@ -456,6 +505,7 @@ pf_status pf_batch_autotune(int32_t n, const int32_t *__restrict h, const int32_
                             const char *path) {
     clear_error();
     if (reps < 1) return fail(PF_EINVAL, "reps must be >= 1");
+    if (n < 1 || !h || !w || !r || !kind) return fail(PF_EINVAL, "bad batch description");
     hipStream_t s = nullptr;
     hipError_t he = hipStreamCreate(&s);
     if (he != hipSuccess) return fail_hip(he, "stream");
@@ -471,8 +521,22 @@ pf_status pf_batch_autotune(int32_t n, const int32_t *__restrict h, const int32_
         pf_batch_plan_destroy(plan);
         return st;
     };
-    bool present[kSizes] = {false, false, false};
-    for (int i = 0; i < n; ++i) present[size_class((int64_t)h[i] * w[i])] = true;
+    // The batch-context keys (kind, radius, size class) this batch uses.
+    std::vector<std::array<int, 3>> keys;
+    {
+        bool seen[2][PF_R_MAX + 1][kSizes] = {};
+        for (int i = 0; i < n; ++i) {
+            if ((kind[i] != PF_KIND_2D && kind[i] != PF_KIND_SEP) || r[i] < 0 || r[i] > PF_R_MAX || h[i] < 1 ||
+                w[i] < 1) {
+                (void)hipStreamDestroy(s);
+                return fail(PF_EINVAL, "bad image " + std::to_string(i));
+            }
+            bool &b = seen[kind[i]][r[i]][size_class((int64_t)h[i] * w[i])];
+            if (!b) keys.push_back({kind[i], r[i], size_class((int64_t)h[i] * w[i])});
+            b = true;
+        }
+        std::sort(keys.begin(), keys.end());
+    }
     float best = 0.0f;
     pf_status st = measure(&best);
     // Workgroups per compute unit first (the whole batch moves together).
@@ -493,35 +557,39 @@ pf_status pf_batch_autotune(int32_t n, const int32_t *__restrict h, const int32_
             g_table.batch_blocks_per_cu = keep;
         }
     }
+    // Coordinate descent over the batch-context keys the batch uses, one key
+    // at a time: a new tile height is kept only when the whole batch gets at
+    // least 3% faster. Single-image entries are not touched.
     const int bys[] = {8, 16, 32, 64};
-    // Coordinate descent: one size class at a time, every radius and both
-    // FP32 kinds of that class move together; a new tile height is kept
-    // only when the whole batch gets at least 3% faster.
-    for (int sc = 0; sc < kSizes && st == PF_OK; ++sc) {
-        if (!present[sc]) continue;
+    for (const auto &k : keys) {
+        if (st != PF_OK) break;
         for (int by : bys) {
-            Table saved;
+            int keep = 0;
             {
                 std::lock_guard<std::mutex> lk(g_mu);
-                saved = g_table;
-                for (int k = 0; k < 2; ++k)
-                    for (int rr = 0; rr <= PF_R_MAX; ++rr) g_table.e[k][rr][sc].rows_per_wave = by;
+                pf_tune_entry &e = g_table.e[PF_TUNE_BATCH][k[0]][k[1]][k[2]];
+                if (e.rows_per_wave == by) continue;
+                keep = e.rows_per_wave;
+                e.rows_per_wave = by;
             }
             float us = 0.0f;
             st = measure(&us);
-            if (st != PF_OK || !(us < 0.97f * best)) {
-                std::lock_guard<std::mutex> lk(g_mu);
-                g_table = saved;
-            } else {
+            if (st == PF_OK && us < 0.97f * best) {
                 best = us;
+            } else {
                 std::lock_guard<std::mutex> lk(g_mu);
-                for (int k = 0; k < 2; ++k)
-                    for (int rr = 0; rr <= PF_R_MAX; ++rr) g_table.e[k][rr][sc].us = us;
+                g_table.e[PF_TUNE_BATCH][k[0]][k[1]][k[2]].rows_per_wave = keep;
             }
+            if (st != PF_OK) break;
         }
     }
     (void)hipStreamDestroy(s);
     if (st != PF_OK) return st;
+    {
+        // Each key the batch used records the tuned batch's time.
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (const auto &k : keys) g_table.e[PF_TUNE_BATCH][k[0]][k[1]][k[2]].us = best;
+    }
     if (path) return pf_tune_save(path);
     return PF_OK;
 }

@@ -2,6 +2,7 @@
 include/pf.h declares, and rejects invalid arguments before touching the
 device (host-side validation only; no compute call runs here)."""
 import ctypes
+import glob
 import json
 import os
 import re
@@ -11,13 +12,16 @@ import pytest
 import paper_1302_5586_amd as pf
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "pf.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(pf_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(pf_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -91,26 +95,52 @@ def test_u8_validation(lib):
 def test_tune_table_roundtrip(lib, tmp_path):
     pf.tune_reset()
     e = pf.tune_lookup(pf.KIND_SEP, 2, 4096 * 4096)
-    assert e.variant == pf.VAR_SEPARABLE and e.size_class == 2
+    assert e.variant == pf.VAR_SEPARABLE and e.size_class == 2 and e.context == pf.TUNE_SINGLE
     new = pf.TuneEntry(kind=pf.KIND_2D, r=1, size_class=0, variant=pf.VAR_DIRECT, rows_per_wave=64,
-                       waves_per_group=2, us=1.5)
-    pf.tune_set([new])
+                       waves_per_group=2, us=1.5, context=pf.TUNE_SINGLE)
+    newb = pf.TuneEntry(kind=pf.KIND_SEP, r=3, size_class=1, variant=pf.VAR_SEPARABLE, rows_per_wave=8,
+                        waves_per_group=4, us=2.5, context=pf.TUNE_BATCH)
+    sepd = pf.TuneEntry(kind=pf.KIND_SEP, r=1, size_class=2, variant=pf.VAR_SEP_DIRECT, rows_per_wave=32,
+                        waves_per_group=4, us=3.0, context=pf.TUNE_SINGLE)
+    pf.tune_set([new, newb, sepd])
     assert pf.tune_lookup(pf.KIND_2D, 1, 100).rows_per_wave == 64
+    # the two contexts are separate keys
+    assert pf.tune_lookup(pf.KIND_2D, 1, 100, pf.TUNE_BATCH).rows_per_wave == 16
+    assert pf.tune_lookup(pf.KIND_SEP, 3, 600 * 700, pf.TUNE_BATCH).rows_per_wave == 8
+    assert pf.tune_lookup(pf.KIND_SEP, 3, 600 * 700).rows_per_wave == 32
     path = str(tmp_path / "tune.json")
     pf.tune_save(path)
     doc = json.load(open(path))
-    assert len(doc["entries"]) == 3 * 9 * 3
+    # single-image entries for 3 kinds, batch entries for the 2 FP32 kinds
+    assert len(doc["entries"]) == 3 * 9 * 3 + 2 * 9 * 3
     pf.tune_reset()
     assert pf.tune_lookup(pf.KIND_2D, 1, 100).rows_per_wave != 64
     pf.tune_load(path)
     got = pf.tune_lookup(pf.KIND_2D, 1, 100)
     assert (got.rows_per_wave, got.waves_per_group) == (64, 2)
-    with pytest.raises(pf.PFInvalid):
+    assert pf.tune_lookup(pf.KIND_SEP, 3, 600 * 700, pf.TUNE_BATCH).rows_per_wave == 8
+    assert pf.tune_lookup(pf.KIND_SEP, 1, 4096 * 4096).variant == pf.VAR_SEP_DIRECT
+    # a file written before contexts existed loads as single-image entries
+    for d in doc["entries"]:
+        d.pop("context")
+    old = str(tmp_path / "old.json")
+    json.dump({"entries": [d for d in doc["entries"][:3 * 9 * 3]]}, open(old, "w"))
+    pf.tune_load(old)
+    assert pf.tune_lookup(pf.KIND_2D, 1, 100).rows_per_wave == 64
+    with pytest.raises(pf.PFInvalid):   # batches never run separable filters as 2D taps
         pf.tune_set([pf.TuneEntry(kind=pf.KIND_SEP, r=3, size_class=0, variant=pf.VAR_SEP_DIRECT,
-                                  rows_per_wave=16, waves_per_group=4)])
+                                  rows_per_wave=16, waves_per_group=4, context=pf.TUNE_BATCH)])
+    with pytest.raises(pf.PFInvalid):   # batch kernels run four waves per workgroup
+        pf.tune_set([pf.TuneEntry(kind=pf.KIND_SEP, r=3, size_class=0, variant=pf.VAR_SEPARABLE,
+                                  rows_per_wave=16, waves_per_group=2, context=pf.TUNE_BATCH)])
+    with pytest.raises(pf.PFInvalid):
+        pf.tune_set([pf.TuneEntry(kind=pf.KIND_U8, r=3, size_class=0, variant=pf.VAR_DIRECT,
+                                  rows_per_wave=16, waves_per_group=4, context=pf.TUNE_BATCH)])
     with pytest.raises(pf.PFInvalid):
         pf.tune_set([pf.TuneEntry(kind=pf.KIND_2D, r=1, size_class=0, variant=pf.VAR_DIRECT,
                                   rows_per_wave=12, waves_per_group=4)])
+    with pytest.raises(pf.PFInvalid):
+        pf.tune_lookup(pf.KIND_U8, 1, 100, pf.TUNE_BATCH)
     pf.tune_reset()
 
 
