@@ -156,6 +156,21 @@ pf_status pf_sum_workspace(int64_t n, PF_OUTP(size_t, bytes));
 pf_status pf_sum_f32(int64_t n, PF_ARR(const float, x, n), PF_ARR(double, out, 2),
                      void *workspace, size_t workspace_bytes, void *stream);
 
+/* ---- reductions: sum and mean without any allocation --------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and the same bits as pf_sum_f32, with the chunk partials in a
+ * static device array of the library (64 KiB on each GPU it runs on, held
+ * until the process ends) instead of a caller workspace. n >= 1 and at most
+ * 2^29 (8192 chunks of 65536 elements; larger n: PF_EUNSUPPORTED). x:
+ * float[n] device, 4-byte aligned; out: double[2] device, 8-byte aligned;
+ * x and out disjoint (else PF_EALIAS). Two launches on `stream`; calls no
+ * hipMalloc, hipFree or allocating library routine. Every call on one GPU
+ * shares that GPU's scratch, so calls that overlap in time on one GPU (on
+ * different streams, or from several threads) race and must be ordered by
+ * the caller; nothing in the scratch needs to start at zero. */
+pf_status pf_sum_f32_noalloc(int64_t n, PF_ARR(const float, x, n), PF_ARR(double, out, 2), void *stream);
+
 /* ---- reductions: 256-bin histogram of a uint8 array ----------------------
  * The indirect increment A[t[i]]++ of the `independent` example
  * (Sec. II-B.3) with repeated indices: hist[v] = number of i with

@@ -104,6 +104,7 @@ _SIGS = {
     "pf_inc_plan_destroy": (_I32, [_P]),
     "pf_edge_inc_atomic_f64": (_I32, [_I32, _I32, _P, _P, _P, _P]),
     "pf_sum_f32": (_I32, [_I64, _P, _P, _P, ctypes.c_size_t, _P]),
+    "pf_sum_f32_noalloc": (_I32, [_I64, _P, _P, _P]),
     "pf_hist_workspace": (_I32, [_I64, _P]),
     "pf_hist256_u8": (_I32, [_I64, _P, _P, _P, ctypes.c_size_t, _P]),
     "pf_filter_chain_f32": (_I32, [_I32, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
@@ -280,6 +281,20 @@ def sum_f32(x, *, out=None, workspace=None, stream=None):
         workspace = _workspace(load().pf_sum_workspace, n, x.device)
     _check(load().pf_sum_f32(n, x.data_ptr(), out.data_ptr(), workspace.data_ptr(),
                              workspace.numel() * workspace.element_size(), _stream_ptr(stream)))
+    return out
+
+
+def sum_f32_noalloc(x, *, out=None, stream=None):
+    """The sum and mean of ``sum_f32`` (same bits) with no workspace: the
+    library's static device scratch holds the partials (x up to 2^29
+    elements). Calls that overlap in time on one GPU share that scratch and
+    must be ordered by the caller."""
+    torch = _torch()
+    if not x.is_cuda or x.dtype != torch.float32 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous CUDA float32 tensor")
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=x.device)
+    _check(load().pf_sum_f32_noalloc(x.numel(), x.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
     return out
 
 

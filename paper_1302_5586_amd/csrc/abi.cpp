@@ -184,6 +184,25 @@ pf_status pf_sum_f32(int64_t n, const float *x, double *out, void *workspace, si
     return PF_OK;
 }
 
+pf_status pf_sum_f32_noalloc(int64_t n, const float *x, double *out, void *stream) {
+    clear_error();
+    if (n < 1) return fail(PF_EINVAL, "n must be >= 1");
+    if (n > sum_noalloc_max())
+        return fail(PF_EUNSUPPORTED, "n exceeds the static scratch capacity of " + std::to_string(sum_noalloc_max()) +
+                                         " elements (use pf_sum_f32 with a workspace)");
+    if (!x || !out) return fail(PF_EINVAL, "null pointer");
+    if ((uintptr_t)x % 4) return fail(PF_EINVAL, "x must be 4-byte aligned");
+    if ((uintptr_t)out % 8) return fail(PF_EINVAL, "out must be 8-byte aligned");
+    if (overlap(x, (size_t)n * sizeof(float), out, 2 * sizeof(double)))
+        return fail(PF_EALIAS, "x and out must not overlap (restrict)");
+    void *ws = nullptr;
+    hipError_t e = sum_scratch(&ws);
+    if (e != hipSuccess) return fail_hip(e, "static scratch address");
+    e = launch_sum(x, n, out, ws, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "kernel launch");
+    return PF_OK;
+}
+
 pf_status pf_hist_workspace(int64_t n, size_t *bytes) {
     clear_error();
     if (!bytes) return fail(PF_EINVAL, "null output");

@@ -185,6 +185,10 @@ size_t sum_workspace_bytes(int64_t n);
 size_t hist_workspace_bytes(int64_t n);
 hipError_t launch_sum(const float *x, int64_t n, double *out, void *workspace, hipStream_t s);
 hipError_t launch_hist(const uint8_t *x, int64_t n, int64_t *hist, void *workspace, hipStream_t s);
+// The sum's static device scratch (reduce.hip): its capacity in elements and
+// its address on the current device.
+int64_t sum_noalloc_max();
+hipError_t sum_scratch(void **ptr);
 // Workgroups of the batch kernel that fit on the device at once.
 int batch_grid_limit(int group, bool exact, int mask, int wpg);
 void *batch_kernel_fn(int group, bool exact, int mask);

@@ -19,6 +19,8 @@
 // Both run as two launches over a caller-provided workspace (chunk partials,
 // per-block sub-histograms), so nothing is allocated and nothing needs
 // zeroing.
+#include <mutex>
+
 #include "dev_common.h"
 #include "pf_internal.h"
 
@@ -219,6 +221,37 @@ int hist_blocks(int64_t n) {
 }
 
 size_t hist_workspace_bytes(int64_t n) { return (size_t)hist_blocks(n) * 256 * sizeof(uint32_t); }
+
+// Scratch of pf_sum_f32_noalloc: the chunk partials of sums of up to
+// kScratchChunks * kChunk elements, in a file-scope device array (64 KiB on
+// each GPU the library runs on, held until the process ends). In host code
+// `scratch` names a host-side stand-in, not device memory: host code uses
+// only the per-device address that hipGetSymbolAddress returns.
+constexpr int64_t kScratchChunks = 8192;
+static __device__ __align__(256) double scratch[kScratchChunks];
+
+int64_t sum_noalloc_max() { return kScratchChunks * red::kChunk; }
+
+// The device address of `scratch` on the current device, looked up once per
+// device with that device current.
+hipError_t sum_scratch(void **ptr) {
+    static std::mutex mu;
+    static void *addr[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_sum(const float *x, int64_t n, double *out, void *workspace, hipStream_t s) {
     const int64_t nchunks = sum_chunks(n);
