@@ -21,9 +21,15 @@ Printed as one JSON line with, besides the contract fields:
   reduce        float64 sum of 4096x4096 FP32; histogram of 256 MiB uint8;
   inc           OP2 edge-to-cell increment on a 2048x2048 quad mesh;
   rgb_u8        1920x1080 planar RGB 7x7 integer filter;
-  serve         open-loop Poisson arrivals at 2000 req/s (p50/p99/p99.9);
-  cpu_baseline  the C oracle on the host cores (and on one) over whole
-                passes of the batch.
+  small         256x256 3x3 Gaussian: back-to-back throughput and the
+                latency distribution of single calls;
+  *_exact       the bit-reproducible mode (PF_FLAG_EXACT) at 4096x4096 and
+                on the batch, beside the default mode;
+  serve         open-loop Poisson arrivals at 2000 req/s (p50/p99/p99.9),
+                a sweep of arrival rates up to saturation, and upload mode;
+  cpu_baseline  the C oracle on all host cores and on one, over whole
+                passes of the batch; cpu_per_config the same for every
+                configuration.
 """
 from __future__ import annotations
 
@@ -53,12 +59,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--tune", default=os.path.join(ROOT, "paper_1302_5586_amd", "tune_mi355x.json"))
     ap.add_argument("--autotune", default="",
                     help="tune the table (per class, then on the batch workload), write it to this path, and "
                          "bench with it")
-    ap.add_argument("--skip", default="", help="comma list of sections to skip: plain,large,chain,reduce,inc,rgb,serve,cpu")
+    ap.add_argument("--skip", default="",
+                    help="comma list of sections to skip: exact,plain,large,chain,reduce,inc,small,rgb,serve,cpu")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 512 MiB device copy 4 times (reference for counter scaling)")
     return ap.parse_args()
@@ -210,9 +216,26 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_traffic("k_batch_f32_batch512"),
                      "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_source": "profiles/counters.json: rocprofv3 --pmc runs of this kernel source "
+                                       "(null when the kernel sources changed since); not measured in this run",
                      "kernel": "k_batch_f32", "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_kernel_ms": round(k_avg_ms, 4)},
     }
+
+    # ---- the batch in the bit-reproducible mode ----------------------------------
+    if "exact" not in skip:
+        plan_x = pf.BatchPlan(pk.h, pk.w, pk.r, pk.kind, pk.pix_off, pk.filt_off, x.numel(), fl.numel(), graph=True,
+                              exact=True)
+        for _ in range(3):
+            plan_x.run(x, fl, out)
+        ms = time_events(torch, lambda _: plan_x.run(x, fl, out), max(5, args.steps), stream)
+        result["batch_exact"] = {"value": round(px / (ms * 1e-3) / 1e9, 3), "unit": "Gpixel/s",
+                                 "ms_per_step": round(ms, 4), "cost_vs_default": round(ms / k_avg_ms, 3),
+                                 "frac_hbm": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "workload": "the same batch with PF_FLAG_EXACT (separate multiply and add per tap, "
+                                             "bit-identical to the sequential program)"}
+        log("batch exact: %.3f ms (x%.2f of default)" % (ms, ms / k_avg_ms))
+        plan_x.close()
 
     # ---- plain: the same images as single-image launches ---------------------
     if "plain" not in skip:
@@ -275,14 +298,21 @@ def main():
         g1 = torch.from_numpy(cfg.f1d).to(dev)
         g2 = g1.clone()
         for name, fn in (("large_2d", lambda i: pf.filter2d(xs[i % nbuf], f2, out=os_[i % nbuf])),
-                         ("large_sep", lambda i: pf.filter_sep(xs[i % nbuf], g1, g2, out=os_[i % nbuf]))):
+                         ("large_sep", lambda i: pf.filter_sep(xs[i % nbuf], g1, g2, out=os_[i % nbuf])),
+                         ("large_2d_exact", lambda i: pf.filter2d(xs[i % nbuf], f2, exact=True, out=os_[i % nbuf])),
+                         ("large_sep_exact",
+                          lambda i: pf.filter_sep(xs[i % nbuf], g1, g2, exact=True, out=os_[i % nbuf]))):
             for i in range(nbuf):
                 fn(i)
             ms = time_events(torch, fn, 64, stream)
             gbs = 8 * n / (ms * 1e-3) / 1e9
             result[name] = {"value": round(n / (ms * 1e-3) / 1e9, 3), "unit": "Gpixel/s", "us_per_call": round(ms * 1e3, 2),
                             "achieved_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
-                            "workload": "4096x4096 FP32, 5x5 Gaussian sigma 1.5, seed 1, buffers rotated over 1 GiB"}
+                            "workload": "4096x4096 FP32, 5x5 Gaussian sigma 1.5, seed 1, buffers rotated over 1 GiB"
+                                        + ("; PF_FLAG_EXACT" if name.endswith("exact") else "")}
+            if name.endswith("exact"):
+                base = result[name[:-len("_exact")]]["us_per_call"]
+                result[name]["cost_vs_default"] = round(ms * 1e3 / base, 3)
             log("%s: %.2f us/call, %.0f GB/s (%.1f%% of HBM)" % (name, ms * 1e3, gbs, 100 * gbs / HBM_PEAK_GBS))
         del xs, os_
 
@@ -389,6 +419,45 @@ def main():
         plan_inc.close()
         del ed, cells, e2c
 
+    # ---- 256x256 3x3 Gaussian: throughput and single-call latency ------------
+    if "small" not in skip:
+        cfg = synth.config_small()
+        n = cfg.h * cfg.w
+        nbuf = 64
+        xs = [torch.from_numpy(cfg.image).to(dev) for _ in range(nbuf)]
+        os_ = [torch.empty_like(xs[0]) for _ in range(nbuf)]
+        f2 = torch.from_numpy(cfg.f2d).to(dev)
+        fn = lambda i: pf.filter2d(xs[i % nbuf], f2, out=os_[i % nbuf])  # noqa: E731
+        for i in range(nbuf):
+            fn(i)
+        ms = time_events(torch, fn, 2000, stream)
+        # single calls: events around each call on its stream, host wall time
+        # from the call to the completion of a synchronize
+        lat_ev, lat_host = [], []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        for i in range(1000):
+            t0 = time.perf_counter()
+            e0.record(stream)
+            fn(i)
+            e1.record(stream)
+            e1.synchronize()
+            lat_host.append((time.perf_counter() - t0) * 1e6)
+            lat_ev.append(e0.elapsed_time(e1) * 1e3)
+        pc = lambda v, q: round(float(np.percentile(v, q)), 2)  # noqa: E731
+        result["small"] = {"value": round(n / (ms * 1e-3) / 1e9, 3), "unit": "Gpixel/s",
+                           "us_per_call_back_to_back": round(ms * 1e3, 3),
+                           "frac_hbm": round(8 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "single_call_event_us": {"p50": pc(lat_ev, 50), "p99": pc(lat_ev, 99),
+                                                    "max": round(max(lat_ev), 2)},
+                           "single_call_host_us": {"p50": pc(lat_host, 50), "p99": pc(lat_host, 99),
+                                                   "max": round(max(lat_host), 2)},
+                           "calls": 1000,
+                           "workload": "256x256 FP32, 3x3 Gaussian sigma 1.0, seed 0; launch-bound (512 KiB)"}
+        log("small: %.2f us/call back to back; single call p50 %.2f us (events), %.2f us (host)" % (
+            ms * 1e3, pc(lat_ev, 50), pc(lat_host, 50)))
+        del xs, os_
+
     # ---- 1080p RGB uint8 7x7 -------------------------------------------------
     if "rgb" not in skip:
         cfg = synth.config_rgb()
@@ -448,67 +517,131 @@ def main():
                                        "(seed 40) sized as the batch; r 1..4; separable Gaussians"}
         log("serve: p50 %.1f us p99 %.1f us, %.3f Gpx/s, mean batch %.2f" % (st["p50_us"], st["p99_us"],
                                                                           st["gpx_per_s"], st["mean_batch"]))
-        # Saturation: about 100,000 requests at 2,000,000 req/s (about 600
-        # Gpx/s offered, above what the GPU can drain) show what continuous
-        # batching sustains; the plain section above is the one-launch-per-
-        # image rate.
-        sat = synth.arrival_trace(rate=2.0e6, duration=0.05, seed=7)
-        fls, foffs = [], np.zeros(sat.n, np.int64)
-        fo = 0
-        for i in range(sat.n):
-            g = synth.gaussian_1d(int(sat.r[i]), float(sat.sigma[i]))
-            fls += [g, g]
-            foffs[i] = fo
-            fo += 2 * g.size
-        pi = sat.pool_index
+        # Arrival-rate sweep up to saturation (about 100,000 requests at
+        # 2,000,000 req/s, about 600 Gpx/s offered, above what the GPU can
+        # drain): what continuous batching sustains as the load grows; the
+        # plain section above is the one-launch-per-image rate.
+        def trace_filters(tr_):
+            fls_, fo_ = [], np.zeros(tr_.n, np.int64)
+            o_ = 0
+            for i in range(tr_.n):
+                g = synth.gaussian_1d(int(tr_.r[i]), float(tr_.sigma[i]))
+                fls_ += [g, g]
+                fo_[i] = o_
+                o_ += 2 * g.size
+            return np.concatenate(fls_), fo_
+
+        sweep = []
+        for rate, secs, seed in ((2.0e4, 3.0, 8), (2.0e5, 0.5, 9), (2.0e6, 0.05, 7)):
+            tr_ = synth.arrival_trace(rate=rate, duration=secs, seed=seed)
+            flt_, fo_ = trace_filters(tr_)
+            pi_ = tr_.pool_index
+            srv = pf.Server(64 << 30, n_streams=4, max_batch=64, max_queue=1 << 20)
+            ss = srv.run_trace((tr_.t * 1e9).astype(np.int64), pool.h[pi_], pool.w[pi_], tr_.r, offs[pi_], fo_,
+                               pool_dev, flt_)
+            srv.close()
+            sweep.append({"offered_req_s": rate, "seconds": secs, "requests": tr_.n,
+                          "offered_gpx_s": round(float((pool.h[pi_].astype(np.float64) * pool.w[pi_]).sum()) / secs
+                                                 / 1e9, 3),
+                          "gpx_per_s": round(ss["gpx_per_s"], 3), "mean_batch": round(ss["mean_batch"], 2),
+                          "p50_us": round(ss["p50_us"], 1), "p99_us": round(ss["p99_us"], 1),
+                          "max_us": round(ss["max_us"], 1)})
+            log("serve at %.0f req/s: %.1f Gpx/s, mean batch %.1f, p50 %.0f us p99 %.0f us" % (
+                rate, ss["gpx_per_s"], ss["mean_batch"], ss["p50_us"], ss["p99_us"]))
+        result["serve_sweep"] = {"points": sweep, "seeds": [8, 9, 7],
+                                 "workload": "open-loop Poisson arrivals at each rate, same pool and request mix; "
+                                             "the last point is past saturation"}
+        result["serve_saturation"] = dict(sweep[-1])
+        # Upload mode: each request's image comes from host memory and is
+        # copied into the server's arena at submit (PCIe-inclusive latency).
+        up_secs = min(10.0, args.serve_seconds)
+        tr_ = synth.arrival_trace(rate=args.serve_rate, duration=up_secs, seed=11)
+        flt_, fo_ = trace_filters(tr_)
+        pi_ = tr_.pool_index
+        host_pool = [pool.images[i] for i in range(pool.n)]
         srv = pf.Server(64 << 30, n_streams=4, max_batch=64, max_queue=1 << 20)
-        ss = srv.run_trace((sat.t * 1e9).astype(np.int64), pool.h[pi], pool.w[pi], sat.r, offs[pi], foffs, pool_dev,
-                           np.concatenate(fls))
+        t_start = time.perf_counter_ns()
+        tickets = []
+        for i in range(tr_.n):
+            due = t_start + int(tr_.t[i] * 1e9)
+            while time.perf_counter_ns() < due:
+                pass
+            k = 2 * int(tr_.r[i]) + 1
+            tickets.append(srv.submit(host_pool[pi_[i]], int(tr_.r[i]), pf.KIND_SEP, flt_[fo_[i]:fo_[i] + 2 * k],
+                                      arrival_ns=0))
+            # release whatever finished (keeps the arena small)
+            while len(tickets) > 256 and srv.poll(tickets[0]):
+                srv.release(tickets.pop(0))
+        for t in tickets:
+            srv.wait(t)
+            srv.release(t)
+        su = srv.stats()
         srv.close()
-        result["serve_saturation"] = {"requests": sat.n, "offered_req_s": 2.0e6, "gpx_per_s": round(ss["gpx_per_s"], 3),
-                                      "mean_batch": round(ss["mean_batch"], 2), "p50_us": round(ss["p50_us"], 1),
-                                      "p99_us": round(ss["p99_us"], 1),
-                                      "workload": "open-loop Poisson at 2,000,000 req/s for 0.05 s (seed 7), same pool"}
-        log("serve saturation: %d requests, %.1f Gpx/s, mean batch %.1f, p50 %.0f us p99 %.0f us" % (
-            sat.n, ss["gpx_per_s"], ss["mean_batch"], ss["p50_us"], ss["p99_us"]))
+        result["serve_upload"] = {"requests": tr_.n, "rate_req_s": args.serve_rate, "seconds": up_secs,
+                                  "p50_us": round(su["p50_us"], 1), "p99_us": round(su["p99_us"], 1),
+                                  "max_us": round(su["max_us"], 1), "gpx_per_s": round(su["gpx_per_s"], 4),
+                                  "mean_batch": round(su["mean_batch"], 2),
+                                  "workload": "as the served stream, but each image submitted from host memory "
+                                              "(copied host to device inside the request; latency measured from "
+                                              "submit)"}
+        log("serve upload: p50 %.1f us p99 %.1f us" % (su["p50_us"], su["p99_us"]))
 
     # ---- CPU baseline: the oracle on one core and on all host cores -----------
     if "cpu" not in skip:
-        # Passes over the 512-image batch with the separable oracle (the
-        # variant the batch runs): one thread for half of cpu_seconds, then
-        # one image per task on a pool of host threads for the other half
-        # (the oracle's C calls release the interpreter lock, so the threads
-        # run in parallel). The oracle itself is unchanged.
-        import concurrent.futures
+        # The oracle's own C functions, unchanged, timed by its OpenMP driver
+        # (oracle/time_oracle.c): one thread, then every host thread this
+        # process may use (bands of output rows with their halo rows, one
+        # image per task for the batch; bit-identical to one thread).
+        # Median of 3 runs each.
+        import platform
 
         import oracle
 
-        def one(i):
-            oracle.filter_sep_f32(b.images[i], b.fx[i], b.fx[i])
-            return b.images[i].size
-
-        def timed(budget, pool=None):
-            spx, passes = 0, 0
-            c0 = time.perf_counter()
-            while passes == 0 or time.perf_counter() - c0 < budget:
-                if pool is None:
-                    spx += sum(one(i) for i in range(b.n))
-                else:
-                    spx += sum(pool.map(one, range(b.n)))
-                passes += 1
-            return spx, passes, time.perf_counter() - c0
-
-        s1, p1, t1 = timed(args.cpu_seconds / 2)
-        cores = max(1, min(len(os.sched_getaffinity(0)), 16))
-        with concurrent.futures.ThreadPoolExecutor(max_workers=cores) as pool:
-            sn, pn, tn = timed(args.cpu_seconds / 2, pool)
-        result["cpu_baseline"] = {"value": round(sn / tn / 1e9, 5), "unit": "Gpixel/s", "cores": cores,
+        cores = len(os.sched_getaffinity(0))
+        model = ""
+        try:
+            for ln in open("/proc/cpuinfo"):
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+        cpu_info = {"nproc": os.cpu_count(), "threads_used": cores, "model": model or platform.processor(),
+                    "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+        bpix = pk.pixels
+        bout = np.empty_like(bpix)
+        t1 = oracle.time_batch_sep(pk.h, pk.w, pk.r, pk.pix_off, bpix, pk.filters, pk.filt_off, bout, 1, 3)
+        tn = oracle.time_batch_sep(pk.h, pk.w, pk.r, pk.pix_off, bpix, pk.filters, pk.filt_off, bout, cores, 3)
+        result["cpu_baseline"] = {"value": round(px / tn / 1e9, 5), "unit": "Gpixel/s", "cores": cores,
                                   "kind": "oracle",
-                                  "sample": "%d full pass(es) over the 512-image batch (%d px), separable C oracle, "
-                                            "one image per task on %d threads, %.1f s" % (pn, sn, cores, tn),
-                                  "one_core": {"value": round(s1 / t1 / 1e9, 5), "unit": "Gpixel/s",
-                                               "sample": "%d pass(es), %d px, %.1f s" % (p1, s1, t1)}}
-        log("cpu oracle: %.4f Gpx/s on %d threads, %.4f Gpx/s on one" % (sn / tn / 1e9, cores, s1 / t1 / 1e9))
+                                  "sample": "the whole 512-image batch (%d px), separable C oracle, one image per "
+                                            "OpenMP task on %d threads, median of 3 passes (%.2f s each)"
+                                            % (px, cores, tn),
+                                  "one_core": {"value": round(px / t1 / 1e9, 5), "unit": "Gpixel/s",
+                                               "sample": "the whole batch on one thread, median of 3 (%.2f s)" % t1},
+                                  "host": cpu_info}
+        log("cpu oracle (batch): %.4f Gpx/s on %d threads, %.4f Gpx/s on one" % (px / tn / 1e9, cores, px / t1 / 1e9))
+        per = {}
+        cs, cl, cu = synth.config_small(), synth.config_large(), synth.config_rgb()
+        cases = (("small_2d", "2d", cs.image, cs.f2d, cs.h * cs.w),
+                 ("large_2d", "2d", cl.image, cl.f2d, cl.h * cl.w),
+                 ("large_sep", "sep", cl.image, np.concatenate([cl.f1d, cl.f1d]), cl.h * cl.w),
+                 ("rgb_u8", "u8", cu.image, cu.filt, cu.image.size))
+        for name, kind, img, flt, npx in cases:
+            o = np.empty_like(img)
+            r1 = oracle.time_image(kind, img, flt, o, 1, 3)
+            rn = oracle.time_image(kind, img, flt, o, cores, 3)
+            per[name] = {"one_core_gpx_s": round(npx / r1 / 1e9, 5), "all_cores_gpx_s": round(npx / rn / 1e9, 5),
+                         "one_core_s": round(r1, 4), "all_cores_s": round(rn, 4), "pixels": int(npx)}
+        per["batch512_sep"] = {"one_core_gpx_s": round(px / t1 / 1e9, 5), "all_cores_gpx_s": round(px / tn / 1e9, 5),
+                               "one_core_s": round(t1, 4), "all_cores_s": round(tn, 4), "pixels": int(px)}
+        if "serve" in result:
+            per["served_capacity"] = {"all_cores_gpx_s": round(px / tn / 1e9, 5),
+                                      "offered_gpx_s": result["serve"]["gpx_per_s"],
+                                      "note": "CPU capacity on the batch's image mix against the served stream's rate"}
+        result["cpu_per_config"] = {"threads": cores, "host": cpu_info, "configs": per}
+        log("cpu per config: %s" % ", ".join("%s %.3f/%.3f" % (k, v["one_core_gpx_s"], v["all_cores_gpx_s"])
+                                              for k, v in per.items() if "one_core_gpx_s" in v))
 
     print(json.dumps(result), flush=True)
 

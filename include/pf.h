@@ -70,6 +70,10 @@ typedef int32_t pf_status;
 
 /* Largest supported filter radius (filters up to 17 x 17). */
 #define PF_R_MAX 8
+/* Largest radius inside batch plans and served requests (9 x 9 filters):
+ * the persistent batch kernel is built only for radii 0..4, where every
+ * body fits in registers; larger radii run as single-image calls. */
+#define PF_BATCH_R_MAX 4
 
 /* Flags for single-image calls, batch plans and servers. */
 #define PF_FLAG_EXACT       0x1  /* separate FP32 mul and add per tap, definition order */

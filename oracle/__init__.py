@@ -26,15 +26,22 @@ _CFLAGS = ["-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-
 _lib = None
 
 
+_TIME_LIB_PATH = os.path.join(_HERE, "liboracle_time.so")
+
+
 def build(verbose: bool = False) -> str:
-    """Compile the C oracle into ``oracle/liboracle.so`` with gcc."""
+    """Compile the C oracle into ``oracle/liboracle.so`` with gcc, and its
+    OpenMP timing driver (the oracle's sources plus ``time_oracle.c``) into
+    ``oracle/liboracle_time.so``."""
     srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
-    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["gcc", *_CFLAGS, "-o", tmp, *srcs, "-lm"]
-    if verbose:
-        print(" ".join(cmd))
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
+    for path, extra, flags in ((_LIB_PATH, [], []),
+                               (_TIME_LIB_PATH, [os.path.join(_HERE, "time_oracle.c")], ["-fopenmp"])):
+        tmp = path + ".tmp%d" % os.getpid()
+        cmd = ["gcc", *_CFLAGS, *flags, "-o", tmp, *srcs, *extra, "-lm"]
+        if verbose:
+            print(" ".join(cmd))
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, path)
     return _LIB_PATH
 
 
@@ -211,3 +218,59 @@ def edge_inc_f64(ncells: int, edge_to_cells, edge_data, cell_data) -> np.ndarray
         raise ValueError("mesh arrays do not match")
     _load().ref_edge_inc_f64(int(ncells), int(ed.size), _p(e2c), _p(ed), _p(cells))
     return cells
+
+
+# ---------------------------------------------------------------- timing
+# The CPU baseline of the benchmark: the oracle's own functions timed on
+# one host thread or on several (OpenMP over bands of output rows, or one
+# image per task for batches; see time_oracle.c). Results are written to
+# `out` and equal the oracle's bit for bit.
+
+_tlib = None
+
+
+def _time_lib():
+    global _tlib
+    if _tlib is not None:
+        return _tlib
+    if not os.path.exists(_TIME_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_TIME_LIB_PATH)
+    P, I = ctypes.c_void_p, ctypes.c_int
+    lib.time_image.argtypes = [I, I, I, I, I, I, P, P, P, I, I]
+    lib.time_image.restype = ctypes.c_double
+    lib.time_batch_sep.argtypes = [I, P, P, P, P, P, P, P, P, I, I]
+    lib.time_batch_sep.restype = ctypes.c_double
+    _tlib = lib
+    return lib
+
+
+def time_image(kind: str, img, filt, out, threads: int, reps: int = 3, shift: int = 6) -> float:
+    """Median seconds of the oracle on one image: kind "2d" (filt: 2D taps),
+    "sep" (filt: fx then fy) or "u8" ([c, h, w] uint8, int8 taps)."""
+    k = {"2d": 0, "sep": 1, "u8": 2}[kind]
+    if k == 2:
+        img = np.ascontiguousarray(img, dtype=np.uint8)
+        c, h, w = img.shape if img.ndim == 3 else (1,) + img.shape
+        filt = np.ascontiguousarray(filt, dtype=np.int8)
+        r = (filt.shape[0] - 1) // 2
+    else:
+        img = _f32(img)
+        c, (h, w) = 1, img.shape
+        filt = _f32(filt).ravel()
+        r = ((int(round(filt.size ** 0.5)) - 1) // 2) if k == 0 else (filt.size // 2 - 1) // 2
+    t = _time_lib().time_image(k, c, h, w, r, int(shift), _p(img), _p(filt), _p(out), int(threads), int(reps))
+    if t < 0:
+        raise MemoryError("oracle timing could not allocate")
+    return t
+
+
+def time_batch_sep(h, w, r, off, pixels, filters, foff, out, threads: int, reps: int = 3) -> float:
+    """Median seconds of the separable oracle over a packed batch (one image per task)."""
+    hh, ww, rr = (np.ascontiguousarray(a, dtype=np.int32) for a in (h, w, r))
+    oo, fo = (np.ascontiguousarray(a, dtype=np.int64) for a in (off, foff))
+    t = _time_lib().time_batch_sep(hh.size, _p(hh), _p(ww), _p(rr), _p(oo), _p(pixels), _p(filters), _p(fo),
+                                   _p(out), int(threads), int(reps))
+    if t < 0:
+        raise MemoryError("oracle timing could not allocate")
+    return t

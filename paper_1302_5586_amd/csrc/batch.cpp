@@ -21,7 +21,7 @@ struct pf_batch_plan {
     int32_t flags = 0;
     int device = -1;
     std::vector<int32_t> variant;  // per image
-    // Two groups: radii 0..4 (index 0) and 5..8 (index 1).
+    // Radius groups: 0 (radii 0..PF_BATCH_R_MAX); index 1 is kept empty.
     int64_t ntasks[2] = {0, 0};
     int32_t grid[2] = {0, 0};
     int32_t mask[2] = {3, 3};  // compiled variant set of each group's kernel
@@ -74,7 +74,7 @@ static hipKernelNodeParams node_params(pf_batch_plan *p, int g, BatchArgs &a) {
 
 // Validates a batch description (sizes, radii, kinds, arena ranges, no two
 // images overlapping) and builds the plan's host tables: per radius group
-// (0..4, 5..8) the image descriptors with their variant and tile height from
+// (all radii are in group 0, 0..PF_BATCH_R_MAX) the image descriptors with their variant and tile height from
 // the batch context of the tune table, and the flat list of wave tiles.
 pf_status build_plan_tables(int32_t n, const int32_t *h, const int32_t *w, const int32_t *r, const int32_t *kind,
                             const int64_t *pix_off, const int64_t *filt_off, int64_t npix, int64_t nfilt,
@@ -90,6 +90,9 @@ pf_status build_plan_tables(int32_t n, const int32_t *h, const int32_t *w, const
         const std::string at = " (image " + std::to_string(i) + ")";
         if (h[i] < 1 || w[i] < 1) return fail(PF_EINVAL, "image sizes must be >= 1" + at);
         if (r[i] < 0 || r[i] > PF_R_MAX) return fail(PF_EINVAL, "radius outside 0.." + std::to_string(PF_R_MAX) + at);
+        if (r[i] > PF_BATCH_R_MAX)
+            return fail(PF_EUNSUPPORTED,
+                        "batches take radii 0.." + std::to_string(PF_BATCH_R_MAX) + " (larger: single-image calls)" + at);
         if (kind[i] != PF_KIND_2D && kind[i] != PF_KIND_SEP) return fail(PF_EINVAL, "unknown filter kind" + at);
         const int64_t px = (int64_t)h[i] * w[i];
         const int64_t k = 2 * r[i] + 1;

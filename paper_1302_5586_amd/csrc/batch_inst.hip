@@ -1,5 +1,5 @@
 // Instantiates one persistent batch kernel, selected by the build:
-//   PF_GROUP: 0 for radii 0..4, 1 for radii 5..8;
+//   PF_GROUP: 0 for radii 0..4 (the only group built);
 //   PF_EXACT: 0 fused multiply-add, 1 separate multiply and add;
 //   PF_VMASK: bit v set if variant v (PF_VAR_*) is compiled in.
 #include "filter_body.h"

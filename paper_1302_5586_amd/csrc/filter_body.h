@@ -100,6 +100,9 @@ __device__ __forceinline__ T *global_at(T *base, int64_t off) {
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
+// Every lambda passed here is marked always_inline: a lambda the inliner
+// leaves as a call keeps the locals it captures by reference on the stack
+// (scratch memory), which the persistent batch kernel must not use.
 template <int B, int E, class F>
 __device__ __forceinline__ void static_for(F &&f) {
     if constexpr (B < E) {
@@ -403,7 +406,7 @@ __device__ __forceinline__ void process_chunk(const Weights<R, VAR> &wt, const R
                                               float (&acc)[2 * R + 1][4], float *__restrict__ out, int w, int xs,
                                               int y0, int i0, bool out_lane) {
     constexpr int K = 2 * R + 1;
-    static_for<0, CH>([&](auto sc) {
+    static_for<0, CH>([&](auto sc) __attribute__((always_inline)) {
         constexpr int s = decltype(sc)::value;
         constexpr int RES = (2 * R + s) % K;
         fold_row_f32<R, VAR, EXACT, RES, -1>(wt, v[s], acc);
@@ -423,7 +426,7 @@ __device__ __forceinline__ void rows_group_f32(const Weights<R, VAR> &wt, const 
                                                int xs, int x0, int lane, int y0, int rows, int i0, int nin,
                                                bool out_lane) {
     constexpr int K = 2 * R + 1;
-    static_for<0, K>([&](auto sc) {
+    static_for<0, K>([&](auto sc) __attribute__((always_inline)) {
         constexpr int s = decltype(sc)::value;
         if (i0 + s < nin) {
             constexpr int RES = (OFF + s) % K;
@@ -464,7 +467,7 @@ __device__ __forceinline__ void rows_pipelined_f32(const Weights<R, VAR> &wt, co
         load_chunk<R, CH, MODE>(in, h, w, xs, x0, lane, y0, i0, last, va);
         if constexpr (R > 0) {
             // Prologue: input rows 0 .. 2R-1 complete no output.
-            static_for<0, 2 * R>([&](auto ic) {
+            static_for<0, 2 * R>([&](auto ic) __attribute__((always_inline)) {
                 constexpr int i = decltype(ic)::value;
                 fold_row_f32<R, VAR, EXACT, i % K, i>(wt, pv[i], acc);
             });
@@ -585,10 +588,10 @@ __global__ __launch_bounds__(512) void k_batch_f32(const BatchImg *__restrict__ 
         const float *fb = fa + 2 * d.r + 1;
         // Only the variants in VMASK are compiled in: the register budget of
         // the kernel is the largest of its bodies.
-        static_for<RLO, RHI + 1>([&](auto rc) {
+        static_for<RLO, RHI + 1>([&](auto rc) __attribute__((always_inline)) {
             constexpr int RR = decltype(rc)::value;
             if (d.r == RR) {
-                static_for<0, 3>([&](auto vc) {
+                static_for<0, 3>([&](auto vc) __attribute__((always_inline)) {
                     constexpr int VV = decltype(vc)::value;
                     if constexpr ((VMASK >> VV) & 1) {
                         if (d.var == VV)
@@ -746,7 +749,7 @@ __device__ __forceinline__ void process_chunk_u8(const WeightsU8<R> &wt, const u
                                                  int (&acc)[2 * R + 1][4], uint8_t *__restrict__ out, int w,
                                                  int shift, int xs, int y0, int i0, bool out_lane) {
     constexpr int K = 2 * R + 1;
-    static_for<0, CH>([&](auto sc) {
+    static_for<0, CH>([&](auto sc) __attribute__((always_inline)) {
         constexpr int s = decltype(sc)::value;
         constexpr int RES = (2 * R + s) % K;
         fold_row_u8<R, RES, -1>(wt, v[s], acc);
@@ -764,7 +767,7 @@ __device__ __forceinline__ void rows_group_u8(const WeightsU8<R> &wt, const uint
                                               uint8_t *__restrict__ out, int (&acc)[2 * R + 1][4], int h, int w,
                                               int shift, int xs, int y0, int rows, int i0, int nin, bool out_lane) {
     constexpr int K = 2 * R + 1;
-    static_for<0, K>([&](auto sc) {
+    static_for<0, K>([&](auto sc) __attribute__((always_inline)) {
         constexpr int s = decltype(sc)::value;
         if (i0 + s < nin) {
             constexpr int RES = (OFF + s) % K;
@@ -799,7 +802,7 @@ __device__ __forceinline__ void rows_u8(const WeightsU8<R> &wt, const uint8_t *_
         uint32_t va[CH], vb[CH];
         load_chunk_u8<R, CH, MODE>(in, h, w, xs, y0, i0, last, va);
         if constexpr (R > 0) {
-            static_for<0, 2 * R>([&](auto ic) {
+            static_for<0, 2 * R>([&](auto ic) __attribute__((always_inline)) {
                 constexpr int i = decltype(ic)::value;
                 fold_row_u8<R, i % K, i>(wt, pv[i], acc);
             });

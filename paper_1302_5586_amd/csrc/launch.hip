@@ -39,7 +39,7 @@ hipError_t launch_u8(int r, const uint8_t *in, const int8_t *filt, uint8_t *out,
 }
 
 void *batch_kernel_fn(int group, bool exact, int mask) {
-    if (group == 1) return exact ? batch_fn<1, 1, 3>() : batch_fn<1, 0, 3>();
+    if (group != 0) return nullptr;
     switch (mask) {
         case 1: return exact ? batch_fn<0, 1, 1>() : batch_fn<0, 0, 1>();
         case 2: return exact ? batch_fn<0, 1, 2>() : batch_fn<0, 0, 2>();
@@ -49,8 +49,9 @@ void *batch_kernel_fn(int group, bool exact, int mask) {
 
 int batch_grid_limit(int group, bool exact, int mask, int wpg) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel_fn(group, exact, mask), wpg * dev::kLanes,
-                                                     0) != hipSuccess ||
+    void *fn = batch_kernel_fn(group, exact, mask);
+    if (!fn ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, wpg * dev::kLanes, 0) != hipSuccess ||
         blocks < 1)
         blocks = 1;
     return blocks * dev_info().cus;
@@ -66,7 +67,7 @@ int batch_grid(int group, bool exact, int mask, int wpg, int64_t ntiles) {
 hipError_t launch_batch(int group, bool exact, int mask, const BatchImg *imgs, const BatchTask *tasks, int ntasks,
                         int grid, int wpg, const float *in, const float *filt, float *out, hipStream_t s) {
 #define PF_LB(G, E, M) launch_batch_g<G, E, M>(imgs, tasks, ntasks, grid, wpg, in, filt, out, s)
-    if (group == 1) return exact ? PF_LB(1, 1, 3) : PF_LB(1, 0, 3);
+    if (group != 0) return hipErrorInvalidValue;
     switch (mask) {
         case 1: return exact ? PF_LB(0, 1, 1) : PF_LB(0, 0, 1);
         case 2: return exact ? PF_LB(0, 1, 2) : PF_LB(0, 0, 2);

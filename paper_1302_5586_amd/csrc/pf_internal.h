@@ -128,7 +128,7 @@ inline void append_tiles(std::vector<BatchTask> &list, int32_t img, const BatchI
 }
 
 // Host tables of a batch plan (batch.cpp): per radius group (0: r 0..4,
-// 1: r 5..8) the image descriptors and the flat wave-tile list, the variant
+// 1: unused, radii above PF_BATCH_R_MAX are rejected) the image descriptors and the flat wave-tile list, the variant
 // of each image, and the variant set each group uses.
 struct PlanTables {
     std::vector<BatchImg> imgs[2];
@@ -170,8 +170,9 @@ hipError_t launch_f32(int r, int var, bool exact, const float *in, const float *
                       int h, int w, int by, int wpg, hipStream_t s);
 hipError_t launch_u8(int r, const uint8_t *in, const int8_t *filt, uint8_t *out, int c, int h,
                      int w, int shift, int by, int wpg, hipStream_t s);
-// Persistent batch kernel over images with r <= 4 (group 0) or r in 5..8
-// (group 1), compiled with the variants of `mask` (see batch_mask).
+// Persistent batch kernel over images with r <= 4 (group 0; group 1 is not
+// built and fails with hipErrorInvalidValue), compiled with the variants of
+// `mask` (see batch_mask).
 hipError_t launch_batch(int group, bool exact, int mask, const BatchImg *imgs, const BatchTask *tasks,
                         int ntasks, int grid, int wpg, const float *in, const float *filt, float *out,
                         hipStream_t s);
@@ -213,8 +214,8 @@ PF_DECL_RADIUS(8)
 #undef PF_DECL_RADIUS
 
 // Batch kernels per (radius group, exact, variant mask), each in its own
-// unit. Masks: bit v for variant v; group 0 has masks 1 (direct only),
-// 2 (separable only) and 3 (both); group 1 has mask 3. The separable-as-2D
+// unit. Masks: bit v for variant v: 1 (direct only), 2 (separable only)
+// and 3 (both). Only group 0 (radii 0..PF_BATCH_R_MAX) is built. The separable-as-2D
 // variant is not compiled into batch kernels (it runs in single-image calls
 // only) so that the persistent kernel stays small.
 template <int G, int E, int M>
@@ -234,8 +235,6 @@ PF_DECL_BATCH(0, 0, 2)
 PF_DECL_BATCH(0, 1, 2)
 PF_DECL_BATCH(0, 0, 3)
 PF_DECL_BATCH(0, 1, 3)
-PF_DECL_BATCH(1, 0, 3)
-PF_DECL_BATCH(1, 1, 3)
 #undef PF_DECL_BATCH
 
 // Smallest compiled variant mask of a group that covers `used` (bit v set

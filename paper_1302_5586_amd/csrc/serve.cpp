@@ -360,6 +360,8 @@ pf_status make_request(pf_server *s, int32_t h, int32_t w, int32_t r, int32_t ki
                        const float *filt, int64_t arrival_ns, std::shared_ptr<Request> *out) {
     if (h < 1 || w < 1) return fail(PF_EINVAL, "image sizes must be >= 1");
     if (r < 0 || r > PF_R_MAX) return fail(PF_EINVAL, "radius outside 0.." + std::to_string(PF_R_MAX));
+    if (r > PF_BATCH_R_MAX)
+        return fail(PF_EUNSUPPORTED, "served requests take radii 0.." + std::to_string(PF_BATCH_R_MAX));
     if (kind != PF_KIND_2D && kind != PF_KIND_SEP) return fail(PF_EINVAL, "unknown filter kind");
     if (!in || !filt) return fail(PF_EINVAL, "null pointer");
     if (!in_is_host && (uintptr_t)in % 4) return fail(PF_EINVAL, "device input must be 4-byte aligned");

@@ -467,7 +467,7 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
                 if (st != PF_OK) break;
                 out.push_back(best);
                 // ---- batch kernel: tile heights, on a batch of n class images
-                if (kind == PF_KIND_U8) continue;
+                if (kind == PF_KIND_U8 || r > PF_BATCH_R_MAX) continue;
                 pf_tune_entry bb = default_entry(PF_TUNE_BATCH, kind, r, sc);
                 bb.us = INFINITY;
                 for (int by : {bb.rows_per_wave, 8, 32, 64}) {
@@ -526,7 +526,7 @@ pf_status pf_batch_autotune(int32_t n, const int32_t *__restrict h, const int32_
     {
         bool seen[2][PF_R_MAX + 1][kSizes] = {};
         for (int i = 0; i < n; ++i) {
-            if ((kind[i] != PF_KIND_2D && kind[i] != PF_KIND_SEP) || r[i] < 0 || r[i] > PF_R_MAX || h[i] < 1 ||
+            if ((kind[i] != PF_KIND_2D && kind[i] != PF_KIND_SEP) || r[i] < 0 || r[i] > PF_BATCH_R_MAX || h[i] < 1 ||
                 w[i] < 1) {
                 (void)hipStreamDestroy(s);
                 return fail(PF_EINVAL, "bad image " + std::to_string(i));

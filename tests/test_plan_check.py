@@ -72,7 +72,7 @@ def _ragged_widths():
     return sorted(v for v in out if v >= 1)
 
 
-@pytest.mark.parametrize("r", range(0, pf.PF_R_MAX + 1))
+@pytest.mark.parametrize("r", range(0, pf.PF_BATCH_R_MAX + 1))
 def test_mixed_shapes_every_radius(lib, r):
     widths = _ragged_widths()
     heights = [1, 2, 3, 5, 17, 33, 64, 65, 129]
@@ -96,7 +96,7 @@ def test_random_mixed_batch(lib):
     n = 400
     h = rng.integers(1, 700, n).astype(np.int32)
     w = rng.integers(1, 1100, n).astype(np.int32)
-    rr = rng.integers(0, pf.PF_R_MAX + 1, n).astype(np.int32)
+    rr = rng.integers(0, pf.PF_BATCH_R_MAX + 1, n).astype(np.int32)
     kinds = rng.integers(0, 2, n).astype(np.int32)
     po, fo, npix, nfilt = _layout(h, w, rr, kinds)
     got = pf.batch_plan_check(h, w, rr, kinds, po, fo, npix, nfilt, no_tune=True)
@@ -109,3 +109,16 @@ def test_random_mixed_batch(lib):
     bad[1] = bad[0]
     with pytest.raises(pf.PFAlias):
         pf.batch_plan_check(h, w, rr, kinds, bad, fo, npix, nfilt)
+
+
+def test_batch_radius_limit(lib):
+    """Batches take radii 0..PF_BATCH_R_MAX; larger radii are refused
+    before anything is built (they run as single-image calls)."""
+    h = np.array([9, 9], np.int32)
+    w = np.array([9, 9], np.int32)
+    kinds = np.array([pf.KIND_2D, pf.KIND_SEP], np.int32)
+    for r in (pf.PF_BATCH_R_MAX + 1, pf.PF_R_MAX):
+        rr = np.array([1, r], np.int32)
+        po, fo, npix, nfilt = _layout(h, w, rr, kinds)
+        with pytest.raises(pf.PFUnsupported):
+            pf.batch_plan_check(h, w, rr, kinds, po, fo, npix, nfilt)
