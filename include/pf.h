@@ -229,8 +229,10 @@ pf_status pf_filter_sep_f32(int32_t h, int32_t w, int32_t r,
                             int32_t flags, void *stream);
 
 /* ---- single image: uint8 planar, integer ----------------------------------
- * c planes of h x w uint8 (plane p at offset p*h*w), one int8 filter for
- * all planes: acc = sum of int8 weight * uint8 pixel in int32 (exact),
+ * The same stencil loop nest (Sec. II, stencils as regular algorithms; the
+ * image-processing domain of Sec. I) in integer arithmetic, with the
+ * calling convention of Sec. II-B.1. c planes of h x w uint8 (plane p at
+ * offset p*h*w), one int8 filter for all planes: acc = sum of int8 weight * uint8 pixel in int32 (exact),
  * q = acc >> shift (arithmetic, i.e. floor), out = min(max(q, 0), 255).
  * c, h, w >= 1; 0 <= r <= PF_R_MAX; 0 <= shift <= 31. in and out disjoint.
  * filt: int8[(2r+1)^2] device. flags must be 0. */
@@ -321,6 +323,10 @@ pf_status pf_batch_autotune(int32_t n,
                             PF_ARR(float, out, npix), int32_t reps, const char *path);
 
 /* ---- batch: many images, one persistent launch ---------------------------
+ * Arrays plus per-item offsets instead of arrays of pointers, the form the
+ * paper gives OP2's rewritten kernel (Sec. III-A); every output element of
+ * every image is an independent iteration (Sec. II-B.3), so all images'
+ * tiles run in one launch. Radii 0..PF_BATCH_R_MAX (else PF_EUNSUPPORTED).
  * n images described by host arrays (sizes first): image i has h[i] x w[i]
  * pixels at in + pix_off[i] and out + pix_off[i], radius r[i], filter kind
  * kind[i] with weights at filt + filt_off[i]. Offsets are in elements.
@@ -355,13 +361,20 @@ pf_status pf_batch_plan_info(const pf_batch_plan *plan, PF_OUTP(int64_t, tasks),
 pf_status pf_batch_plan_destroy(pf_batch_plan *plan);
 
 /* ---- serving: continuous batching under an HBM budget ----------------------
- * A server owns a device arena of `hbm_budget_bytes` (outputs, uploaded
- * inputs, weights), `n_streams` HIP streams and an engine thread. Requests
- * are admitted first-come first-served while their bytes fit in the
- * budget; admitted requests are packed into batches of at most
- * `max_batch` images and launched on whichever stream is free, so new
- * arrivals run while earlier batches are still on the device.
- * A request's result does not depend on which batch it lands in. */
+ * Independent calls (Sec. II-B.3) arriving over time share batches: the
+ * filter requests of a batch run in one persistent launch (the batch form
+ * above), its reductions (the `reduction` directive, Sec. II-B.3; OptiML's
+ * sum, Sec. III-B) in the multi-array sum and histogram kernels.
+ * A server owns a device arena of `hbm_budget_bytes` (results, uploaded
+ * inputs), `n_streams` HIP streams with their descriptor and workspace
+ * buffers (allocated at creation) and an engine thread. Requests are
+ * admitted first-come first-served while their bytes fit in the budget;
+ * admitted requests are packed into batches of at most `max_batch` requests
+ * and launched on whichever stream is free, so new arrivals run while
+ * earlier batches are still on the device. A request's result does not
+ * depend on which batch it lands in: filters as the single-image call with
+ * the same variant, sums and histograms bit for bit as pf_sum_f32 and
+ * pf_hist256_u8. Served filter radii: 0..PF_BATCH_R_MAX. */
 typedef struct pf_server pf_server;
 
 typedef struct pf_server_stats {
@@ -376,20 +389,33 @@ typedef struct pf_server_stats {
     double  gpx_per_s;            /* pixels / wall_s / 1e9                     */
 } pf_server_stats;
 
-/* n_streams 1..8, max_batch 1..4096, max_queue >= 1 (waiting requests). */
+/* n_streams 1..8, max_batch 1..4096, max_queue >= 1 (waiting requests).
+ * flags: 0 or PF_FLAG_EXACT (filters in the bit-reproducible mode). */
 pf_status pf_server_create(int64_t hbm_budget_bytes, int32_t n_streams, int32_t max_batch,
                            int32_t max_queue, int32_t flags, PF_OUTP(pf_server *, srv));
-/* Submit one request (sizes first). `in` is float[h*w]: a device pointer
- * that stays resident and unmodified until the request completes, or, if
- * in_is_host != 0, a host pointer copied into the arena before submit
- * returns. `filt` is a HOST array of the kind's weights, copied. The
- * arrival time (ns on CLOCK_MONOTONIC; 0 = now) is the origin of the
- * request's latency. PF_EBUDGET if the request alone exceeds the budget,
- * PF_EAGAIN if max_queue requests are already waiting. */
+/* Submit one filter request (sizes first). `in` is float[h*w]: a device
+ * pointer that stays allocated and unmodified until the request completes,
+ * or, if in_is_host != 0, a host pointer copied before submit returns.
+ * For a device input, `stream` (a hipStream_t; NULL is the null stream) is
+ * the stream whose queued work produces `in`: the server's launch waits for
+ * the work queued there at submit time. `filt` is a HOST array of the
+ * kind's weights, copied. The arrival time (ns on CLOCK_MONOTONIC; 0 = now)
+ * is the origin of the request's latency. PF_EBUDGET if the request alone
+ * exceeds the budget, PF_EAGAIN if max_queue requests are already waiting,
+ * PF_EUNSUPPORTED for r > PF_BATCH_R_MAX. */
 pf_status pf_server_submit(pf_server *s, int32_t h, int32_t w, int32_t r, int32_t kind,
                            const float *in, int32_t in_is_host,
-                           const float *filt, int64_t arrival_ns,
+                           const float *filt, void *stream, int64_t arrival_ns,
                            PF_OUTP(int64_t, ticket));
+/* Reductions served beside the filters. */
+#define PF_OP_SUM_F32  1   /* sum and mean of float[n]: result double[2]      */
+#define PF_OP_HIST_U8  2   /* 256-bin histogram of uint8_t[n]: int64_t[256]   */
+/* Submit one reduction of n elements (1 <= n <= 2^40): `in` as for
+ * pf_server_submit (device pointer ordered after `stream`, 4-byte aligned
+ * for PF_OP_SUM_F32; or host memory, copied). Same statuses as
+ * pf_server_submit. */
+pf_status pf_server_submit_reduce(pf_server *s, int32_t op, int64_t n, const void *in, int32_t in_is_host,
+                                  void *stream, int64_t arrival_ns, PF_OUTP(int64_t, ticket));
 /* done = 1 once the request's output is complete on the device. */
 pf_status pf_server_poll(pf_server *s, int64_t ticket, PF_OUTP(int32_t, done));
 /* Block until done or timeout (ns; < 0 waits forever): PF_ETIMEDOUT. */
@@ -398,22 +424,30 @@ pf_status pf_server_wait(pf_server *s, int64_t ticket, int64_t timeout_ns);
  * else device) and release the request's arena bytes and ticket. */
 pf_status pf_server_result(pf_server *s, int64_t ticket, int32_t h, int32_t w,
                            float *out, int32_t out_is_host);
+/* Copy a finished reduction's result (double[2] for PF_OP_SUM_F32,
+ * int64_t[256] for PF_OP_HIST_U8; host if out_is_host, else device) and
+ * release it. `op` must be the request's. */
+pf_status pf_server_result_reduce(pf_server *s, int64_t ticket, int32_t op, void *out, int32_t out_is_host);
 /* Release a finished request without copying its output. */
 pf_status pf_server_release(pf_server *s, int64_t ticket);
 pf_status pf_server_stats_get(pf_server *s, PF_OUTP(pf_server_stats, st));
-/* Open-loop load generator: submit n requests at their scheduled times
+/* Open-loop load generator (filter requests only): submit n requests at
+ * their scheduled times
  * (arrival_ns[i], relative to the call's start), request i filtering
  * h[i] x w[i] pixels at in + pix_off[i] (device arena of npix floats) with
  * radius r[i] and host weights filt + filt_off[i] (kind PF_KIND_SEP), and
- * release each output as it completes. Returns when all have completed;
- * latencies are recorded in the server's stats. */
+ * release each output as it completes. The pool must be complete (no work
+ * producing it still queued) when the call starts. Returns when all have
+ * completed; latencies are recorded in the server's stats. */
 pf_status pf_server_run_trace(pf_server *s, int32_t n,
                               PF_ARR(const int64_t, arrival_ns, n),
                               PF_ARR(const int32_t, h, n), PF_ARR(const int32_t, w, n),
                               PF_ARR(const int32_t, r, n),
                               PF_ARR(const int64_t, pix_off, n), PF_ARR(const int64_t, filt_off, n),
                               int64_t npix, const float *in, int64_t nfilt, const float *filt);
-/* Drain in-flight work, then free everything the server owns. */
+/* Stop: requests not yet admitted fail (PF_EAGAIN from wait/poll while the
+ * server exists), admitted ones run to completion; then free everything the
+ * server owns. No call on `s` may run concurrently with or after it. */
 pf_status pf_server_destroy(pf_server *s);
 
 #ifdef __cplusplus

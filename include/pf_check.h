@@ -34,6 +34,16 @@ pf_status pf_batch_plan_check(int32_t n,
                               int64_t npix, int64_t nfilt, int32_t flags,
                               PF_OUTP(int64_t, tiles), PF_OUTP(int64_t, violations));
 
+/* Replays operations on the first-fit allocator that a server uses for its
+ * HBM arena (host bookkeeping only; no device memory is touched): op[i] > 0
+ * allocates op[i] bytes (rounded up to 256), op[i] < 0 frees the allocation
+ * made by operation -op[i] - 1. result[i] is the allocation's offset, or -1
+ * if no free run was large enough; 0 for a free. A free of an operation
+ * that was not a successful, still live allocation: PF_EINVAL. used: the
+ * bytes allocated after the last operation. */
+pf_status pf_arena_replay(int64_t budget, int32_t n, PF_ARR(const int64_t, op, n), PF_ARR(int64_t, result, n),
+                          PF_OUTP(int64_t, used));
+
 #ifdef __cplusplus
 }
 #endif

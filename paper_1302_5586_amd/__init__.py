@@ -33,6 +33,7 @@ BATCH_NO_TUNE = 0x4
 KIND_2D, KIND_SEP, KIND_U8 = 0, 1, 2
 VAR_DIRECT, VAR_SEPARABLE, VAR_SEP_DIRECT = 0, 1, 2
 BORDER_CLAMP, BORDER_ZERO, BORDER_REFLECT, BORDER_MIRROR = 0, 1, 2, 3
+OP_SUM_F32, OP_HIST_U8 = 1, 2
 CHAIN_HALO_MAX = 16
 
 
@@ -128,10 +129,13 @@ _SIGS = {
     "pf_batch_plan_variants": (_I32, [_P, _I32, _P]),
     "pf_batch_plan_info": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "pf_batch_plan_destroy": (_I32, [_P]),
+    "pf_arena_replay": (_I32, [_I64, _I32, _P, _P, ctypes.POINTER(_I64)]),
     "pf_batch_plan_check": (_I32, [_I32, _P, _P, _P, _P, _P, _P, _I64, _I64, _I32, ctypes.POINTER(_I64),
                                    ctypes.POINTER(_I64)]),
     "pf_server_create": (_I32, [_I64, _I32, _I32, _I32, _I32, ctypes.POINTER(_P)]),
-    "pf_server_submit": (_I32, [_P, _I32, _I32, _I32, _I32, _P, _I32, _P, _I64, ctypes.POINTER(_I64)]),
+    "pf_server_submit": (_I32, [_P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P, _I64, ctypes.POINTER(_I64)]),
+    "pf_server_submit_reduce": (_I32, [_P, _I32, _I64, _P, _I32, _P, _I64, ctypes.POINTER(_I64)]),
+    "pf_server_result_reduce": (_I32, [_P, _I64, _I32, _P, _I32]),
     "pf_server_poll": (_I32, [_P, _I64, ctypes.POINTER(_I32)]),
     "pf_server_wait": (_I32, [_P, _I64, _I64]),
     "pf_server_result": (_I32, [_P, _I64, _I32, _I32, _P, _I32]),
@@ -561,6 +565,16 @@ def batch_plan_check(h, w, r, kind, pix_off, filt_off, npix: int, nfilt: int, *,
     return {"tiles": tiles.value, "violations": bad.value}
 
 
+def arena_replay(budget: int, ops) -> tuple:
+    """Host-only replay of the server's first-fit arena allocator (see
+    pf_arena_replay): returns (per-operation results, bytes in use)."""
+    o = _i64(ops)
+    res = np.zeros(o.size, np.int64)
+    used = _I64()
+    _check(load().pf_arena_replay(int(budget), o.size, _np_ptr(o), _np_ptr(res), ctypes.byref(used)))
+    return res, used.value
+
+
 @dataclass
 class PackedBatch:
     """Host-side packing of a list of images and filters into arenas."""
@@ -608,7 +622,13 @@ def pack_batch(images: Sequence[np.ndarray], filters: Sequence[np.ndarray], kind
 # ---------------------------------------------------------------- serving
 
 class Server:
-    """Continuous-batching filter server with an HBM budget."""
+    """Continuous-batching server for filter, sum and histogram requests
+    under an HBM budget.
+
+    A GPU tensor submitted as input is read later by the server's own
+    streams: the server orders that read after the work queued on the
+    current (or given) torch stream at submit, and this object keeps a
+    reference to the tensor until its result is fetched or released."""
 
     def __init__(self, hbm_budget_bytes: int, n_streams: int = 2, max_batch: int = 64, max_queue: int = 1 << 16,
                  flags: int = 0):
@@ -616,24 +636,48 @@ class Server:
         _check(load().pf_server_create(int(hbm_budget_bytes), n_streams, max_batch, max_queue, flags,
                                        ctypes.byref(p)))
         self._s = p
+        self._inputs = {}
 
-    def submit(self, x, r: int, kind: int, filt: np.ndarray, arrival_ns: int = 0) -> int:
-        """Submit one FP32 image: a GPU tensor (kept resident, not copied) or
-        a host numpy array (copied into the server's arena)."""
+    def submit(self, x, r: int, kind: int, filt: np.ndarray, arrival_ns: int = 0, stream=None) -> int:
+        """Submit one FP32 image: a GPU tensor (read in place) or a host numpy
+        array (copied into the server's arena)."""
         f = np.ascontiguousarray(filt, dtype=np.float32).ravel()
         t = _I64()
         if isinstance(x, np.ndarray):
             a = np.ascontiguousarray(x, dtype=np.float32)
             h, w = a.shape
-            _check(load().pf_server_submit(self._s, h, w, r, kind, _np_ptr(a), 1, _np_ptr(f), int(arrival_ns),
+            _check(load().pf_server_submit(self._s, h, w, r, kind, _np_ptr(a), 1, _np_ptr(f), None, int(arrival_ns),
                                            ctypes.byref(t)))
         else:
             torch = _torch()
             _dev_tensor(x, torch.float32, "x", (2,))
             h, w = x.shape
-            _check(load().pf_server_submit(self._s, h, w, r, kind, x.data_ptr(), 0, _np_ptr(f), int(arrival_ns),
-                                           ctypes.byref(t)))
+            _check(load().pf_server_submit(self._s, h, w, r, kind, x.data_ptr(), 0, _np_ptr(f), _stream_ptr(stream),
+                                           int(arrival_ns), ctypes.byref(t)))
+            self._inputs[t.value] = x
         return t.value
+
+    def _submit_reduce(self, op: int, x, dtype, np_dtype, stream, arrival_ns) -> int:
+        t = _I64()
+        if isinstance(x, np.ndarray):
+            a = np.ascontiguousarray(x, dtype=np_dtype).ravel()
+            _check(load().pf_server_submit_reduce(self._s, op, a.size, _np_ptr(a), 1, None, int(arrival_ns),
+                                                  ctypes.byref(t)))
+        else:
+            torch = _torch()
+            _dev_tensor(x, getattr(torch, dtype), "x")
+            _check(load().pf_server_submit_reduce(self._s, op, x.numel(), x.data_ptr(), 0, _stream_ptr(stream),
+                                                  int(arrival_ns), ctypes.byref(t)))
+            self._inputs[t.value] = x
+        return t.value
+
+    def submit_sum(self, x, arrival_ns: int = 0, stream=None) -> int:
+        """Submit the float64 sum and mean of an FP32 array (GPU tensor or numpy)."""
+        return self._submit_reduce(OP_SUM_F32, x, "float32", np.float32, stream, arrival_ns)
+
+    def submit_hist(self, x, arrival_ns: int = 0, stream=None) -> int:
+        """Submit the 256-bin histogram of a uint8 array (GPU tensor or numpy)."""
+        return self._submit_reduce(OP_HIST_U8, x, "uint8", np.uint8, stream, arrival_ns)
 
     def poll(self, ticket: int) -> bool:
         d = _I32()
@@ -648,14 +692,31 @@ class Server:
         if out is None:
             a = np.empty((h, w), np.float32)
             _check(load().pf_server_result(self._s, ticket, h, w, _np_ptr(a), 1))
+            self._inputs.pop(ticket, None)
             return a
         torch = _torch()
         _dev_tensor(out, torch.float32, "out", (2,))
         _check(load().pf_server_result(self._s, ticket, h, w, out.data_ptr(), 0))
+        self._inputs.pop(ticket, None)
         return out
+
+    def result_sum(self, ticket: int) -> np.ndarray:
+        """[sum, mean] (float64) of a finished sum request."""
+        a = np.empty(2, np.float64)
+        _check(load().pf_server_result_reduce(self._s, ticket, OP_SUM_F32, _np_ptr(a), 1))
+        self._inputs.pop(ticket, None)
+        return a
+
+    def result_hist(self, ticket: int) -> np.ndarray:
+        """The 256 int64 counts of a finished histogram request."""
+        a = np.empty(256, np.int64)
+        _check(load().pf_server_result_reduce(self._s, ticket, OP_HIST_U8, _np_ptr(a), 1))
+        self._inputs.pop(ticket, None)
+        return a
 
     def release(self, ticket: int):
         _check(load().pf_server_release(self._s, ticket))
+        self._inputs.pop(ticket, None)
 
     def stats(self) -> dict:
         st = ServerStats()
@@ -667,6 +728,7 @@ class Server:
         image pool (GPU tensor) with host filter weights (fx then fy)."""
         torch = _torch()
         _dev_tensor(pool, torch.float32, "pool")
+        torch.cuda.current_stream().synchronize()  # the pool must be complete before the call
         a, hh, ww, rr = _i64(arrival_ns), _i32(h), _i32(w), _i32(r)
         po, fo = _i64(pix_off), _i64(filt_off)
         fl = np.ascontiguousarray(filters, dtype=np.float32).ravel()
@@ -679,6 +741,7 @@ class Server:
         if getattr(self, "_s", None):
             _check(load().pf_server_destroy(self._s))
             self._s = None
+            self._inputs = {}
 
     def __enter__(self):
         return self

@@ -186,6 +186,25 @@ size_t sum_workspace_bytes(int64_t n);
 size_t hist_workspace_bytes(int64_t n);
 hipError_t launch_sum(const float *x, int64_t n, double *out, void *workspace, hipStream_t s);
 hipError_t launch_hist(const uint8_t *x, int64_t n, int64_t *hist, void *workspace, hipStream_t s);
+// Reduction requests of a server batch (reduce.hip). in / out are absolute
+// device addresses (the input array; double[2] or int64_t[256] result);
+// `first` is the request's first slot in the batch workspace: chunk
+// partials (double) for sums, span sub-histograms (256 x uint32) for
+// histograms; `op` is PF_OP_SUM_F32 or PF_OP_HIST_U8.
+struct ReduceReq {
+    int64_t in, n, out, first;
+    int32_t op, pad;
+};
+// Part `part` (chunk or span) of request `req`.
+struct ReduceTask {
+    int32_t req, part;
+};
+// Chunks (sum) or spans (histogram) of an n-element request.
+int64_t reduce_parts(int op, int64_t n);
+// All sums, then all histograms of a batch: two launches each.
+hipError_t launch_reduce_batch(const ReduceReq *reqs, const int32_t *sum_ids, int nsum, const ReduceTask *sum_tasks,
+                               int n_sum_tasks, const int32_t *hist_ids, int nhist, const ReduceTask *hist_tasks,
+                               int n_hist_tasks, double *partial, uint32_t *sub, hipStream_t s);
 // The sum's static device scratch (reduce.hip): its capacity in elements and
 // its address on the current device.
 int64_t sum_noalloc_max();
