@@ -244,7 +244,7 @@ pf_status pf_filter2d_u8(int32_t c, int32_t h, int32_t w, int32_t r, int32_t shi
 
 /* ---- single image with an explicit launch shape ----------------------------
  * The same computation as the call for `kind`/`variant`, with the launch
- * shape forced: rows_per_wave in {4, 8, 16, 32, 64, 128}, waves_per_group in
+ * shape forced: rows_per_wave a multiple of 4 in 4..128, waves_per_group in
  * {1, 2, 4, 8}. Used by the autotuner and by tests that check results do
  * not depend on the launch shape. kind PF_KIND_2D requires variant
  * PF_VAR_DIRECT; PF_KIND_SEP accepts all three variants. For PF_KIND_SEP,
@@ -290,8 +290,9 @@ pf_status pf_tune_load(const char *path);
 pf_status pf_tune_save(const char *path);
 /* Measure, on the current device with hipEvents (median of `reps` timed
  * runs over rotated buffers), for r in 0..r_max and the three size
- * classes: every (rows_per_wave in {8, 16, 32, 64}) x (waves_per_group in
- * {1, 2, 4, 8}) shape of single-image calls of every kind, and for
+ * classes: every (rows_per_wave in {8, 16, 32, 64}, for PF_KIND_U8 also
+ * 12, 20, 24 and 48) x (waves_per_group in {1, 2, 4, 8}) shape of
+ * single-image calls of every kind, and for
  * PF_KIND_SEP also the PF_VAR_SEP_DIRECT variant at the best shape; and the
  * tile heights {8, 16, 32, 64} of the batch kernel on a batch of class
  * images (FP32 kinds). A candidate replaces the default only when at least

@@ -51,7 +51,7 @@ const DevInfo &dev_info() {
 }
 
 bool valid_shape(int by, int wpg) {
-    const bool by_ok = by == 4 || by == 8 || by == 16 || by == 32 || by == 64 || by == 128;
+    const bool by_ok = by >= 4 && by <= 128 && by % 4 == 0;
     const bool wpg_ok = wpg == 1 || wpg == 2 || wpg == 4 || wpg == 8;
     return by_ok && wpg_ok;
 }

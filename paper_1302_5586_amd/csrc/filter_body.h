@@ -696,6 +696,9 @@ __device__ __forceinline__ void fold_row_u8(const WeightsU8<R> &wt, uint32_t own
             D[k][m] = (int32_t)(sh == 0 ? a : __builtin_amdgcn_alignbyte(b, a, sh));
         }
     }
+    // The row's tap dy = -R is the first term of output slot RES: that
+    // accumulator starts from the bias (128 * sum of weights, undoing the
+    // -128 on every pixel) instead of from a zeroed register.
 #pragma unroll
     for (int dy = -R; dy <= R; ++dy) {
         if (IPRO >= 0 && IPRO - R - dy < 0) continue;
@@ -703,21 +706,25 @@ __device__ __forceinline__ void fold_row_u8(const WeightsU8<R> &wt, uint32_t own
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int m = 0; m < ND; ++m) acc[slot][k] = __builtin_amdgcn_sdot4(D[k][m], wt.wd[dy + R][m], acc[slot][k], false);
+            for (int m = 0; m < ND; ++m) {
+                const int prev = (dy == -R && m == 0) ? wt.bias : acc[slot][k];
+                acc[slot][k] = __builtin_amdgcn_sdot4(D[k][m], wt.wd[dy + R][m], prev, false);
+            }
     }
 }
 
-// Finish 4 outputs (add the bias back, arithmetic shift, saturate) and
-// store them through a buffer resource spanning the row: one dword store in
-// kFast, else four byte stores; bytes at or beyond w and halo lanes
-// (offset outside the range) are dropped by the hardware. No branch.
+// Finish 4 outputs (arithmetic shift, saturate; the bias is already in
+// the sums) and store them through a buffer resource spanning the row: one
+// dword store in kFast, else four byte stores; bytes at or beyond w and
+// halo lanes (offset outside the range) are dropped by the hardware. No
+// branch.
 template <int MODE>
 __device__ __forceinline__ void store_u8(uint8_t *__restrict__ row, int xs, int w, bool out_lane, const int (&a)[4],
-                                         int bias, int shift) {
+                                         int shift) {
     uint32_t pk = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        int q = clampi((a[k] + bias) >> shift, 0, 255);  // arithmetic shift of a signed int
+        int q = clampi(a[k] >> shift, 0, 255);  // arithmetic shift of a signed int
         // Keep each saturated byte opaque until it is packed: fused into the
         // gfx950 packed shift-and-saturate instruction, the pair of bytes
         // came back with the upper half of the dword not cleared, and the
@@ -754,9 +761,7 @@ __device__ __forceinline__ void process_chunk_u8(const WeightsU8<R> &wt, const u
         constexpr int RES = (2 * R + s) % K;
         fold_row_u8<R, RES, -1>(wt, v[s], acc);
         constexpr int done = (RES + 1) % K;
-        store_u8<MODE>(out + (int64_t)(y0 + i0 + s - 2 * R) * w, xs, w, out_lane, acc[done], wt.bias, shift);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc[done][k] = 0;
+        store_u8<MODE>(out + (int64_t)(y0 + i0 + s - 2 * R) * w, xs, w, out_lane, acc[done], shift);
     });
 }
 
@@ -775,9 +780,7 @@ __device__ __forceinline__ void rows_group_u8(const WeightsU8<R> &wt, const uint
             fold_row_u8<R, RES, -1>(wt, v, acc);
             const int j = i0 + s - 2 * R;
             constexpr int done = (RES + 1) % K;
-            if (j >= 0 && j < rows) store_u8<MODE>(out + (int64_t)(y0 + j) * w, xs, w, out_lane, acc[done], wt.bias, shift);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) acc[done][k] = 0;
+            if (j >= 0 && j < rows) store_u8<MODE>(out + (int64_t)(y0 + j) * w, xs, w, out_lane, acc[done], shift);
         }
     });
 }

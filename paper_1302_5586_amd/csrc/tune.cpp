@@ -423,7 +423,11 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
                 const int var = kind == PF_KIND_SEP ? PF_VAR_SEPARABLE : PF_VAR_DIRECT;
                 std::vector<std::pair<int, int>> shapes;
                 shapes.push_back({dflt.rows_per_wave, dflt.waves_per_group});
-                for (int by : bys)
+                // The uint8 kernel is bound by ALU work and by how evenly its
+                // few waves spread over the SIMDs: finer tile heights too.
+                std::vector<int> cand(bys, bys + 4);
+                if (kind == PF_KIND_U8) cand.insert(cand.end(), {12, 20, 24, 48});
+                for (int by : cand)
                     for (int wpg : wpgs)
                         if (by != dflt.rows_per_wave || wpg != dflt.waves_per_group) shapes.push_back({by, wpg});
                 auto time_single = [&](int v, int by, int wpg, float *us) -> pf_status {

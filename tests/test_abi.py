@@ -74,7 +74,9 @@ def test_filter_flags_and_filter_alias(lib):
     assert lib.pf_filter_sep_f32(4, 4, 1, FAKE, 0, FAKE + 64, FAKE + (1 << 20), 0, None) == pf.PF_EINVAL
     assert lib.pf_filter_f32_shaped(4, 4, 1, pf.KIND_2D, pf.VAR_SEPARABLE, 16, 4, FAKE, FAKE + 4096,
                                     FAKE + (1 << 20), 0, None) == pf.PF_EINVAL
-    assert lib.pf_filter_f32_shaped(4, 4, 1, pf.KIND_2D, pf.VAR_DIRECT, 12, 4, FAKE, FAKE + 4096,
+    assert lib.pf_filter_f32_shaped(4, 4, 1, pf.KIND_2D, pf.VAR_DIRECT, 10, 4, FAKE, FAKE + 4096,
+                                    FAKE + (1 << 20), 0, None) == pf.PF_EINVAL
+    assert lib.pf_filter_f32_shaped(4, 4, 1, pf.KIND_2D, pf.VAR_DIRECT, 132, 4, FAKE, FAKE + 4096,
                                     FAKE + (1 << 20), 0, None) == pf.PF_EINVAL
 
 
@@ -138,7 +140,7 @@ def test_tune_table_roundtrip(lib, tmp_path):
                                   rows_per_wave=16, waves_per_group=4, context=pf.TUNE_BATCH)])
     with pytest.raises(pf.PFInvalid):
         pf.tune_set([pf.TuneEntry(kind=pf.KIND_2D, r=1, size_class=0, variant=pf.VAR_DIRECT,
-                                  rows_per_wave=12, waves_per_group=4)])
+                                  rows_per_wave=14, waves_per_group=4)])
     with pytest.raises(pf.PFInvalid):
         pf.tune_lookup(pf.KIND_U8, 1, 100, pf.TUNE_BATCH)
     pf.tune_reset()

@@ -81,7 +81,7 @@ def test_launch_shape_does_not_change_results(kind, var):
     filt = rng.standard_normal(25 if kind == 0 else 10).astype(np.float32)
     x, fd = _t(img, dev), _t(filt, dev)
     outs = [pf.filter_shaped(x, fd, r, kind, var, by, wpg).cpu().numpy()
-            for by in (4, 8, 16, 32, 64, 128) for wpg in (1, 2, 4, 8)]
+            for by in (4, 8, 12, 16, 20, 32, 64, 128) for wpg in (1, 2, 4, 8)]
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
 
@@ -176,3 +176,20 @@ def test_strided_views_rejected():
     y = torch.zeros(16, 16, device=dev)
     with pytest.raises(pf.PFAlias):
         pf.filter2d(y, torch.zeros(3, 3, device=dev), out=y)
+
+
+@pytest.mark.parametrize("by,wpg", [(12, 1), (20, 2), (24, 4), (48, 1), (4, 8)])
+def test_u8_tile_shapes_bit_exact(by, wpg):
+    """The uint8 kernel under other tile heights and group sizes (set
+    through the tune table): still bit-exact on the 1080p RGB config."""
+    dev = device()
+    cfg = synth.config_rgb()
+    ref = oracle.filter2d_u8(cfg.image, cfg.filt, cfg.shift)
+    e = pf.TuneEntry(kind=pf.KIND_U8, r=cfg.r, size_class=2, variant=pf.VAR_DIRECT, rows_per_wave=by,
+                     waves_per_group=wpg, us=0.0, context=pf.TUNE_SINGLE)
+    try:
+        pf.tune_set([e])
+        got = pf.filter2d_u8(_t(cfg.image, dev), _t(cfg.filt, dev), cfg.shift).cpu().numpy()
+    finally:
+        pf.tune_reset()
+    assert np.array_equal(got, ref)
