@@ -46,6 +46,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: dot4 lane-ops/s
+# Server settings for every served run: three streams keep a batch on the
+# device while the next is packed; batches of up to 256 requests keep the
+# per-batch host work small next to the kernel at saturation.
+SERVE_STREAMS = 3
+SERVE_MAX_BATCH = 256
 
 
 def log(msg):
@@ -505,7 +510,7 @@ def main():
         pi = tr.pool_index
         hh, ww = pool.h[pi], pool.w[pi]
         log("serve: %d requests over %.0f s at %.0f req/s" % (tr.n, args.serve_seconds, args.serve_rate))
-        srv = pf.Server(64 << 30, n_streams=4, max_batch=64, max_queue=1 << 20)
+        srv = pf.Server(64 << 30, n_streams=SERVE_STREAMS, max_batch=SERVE_MAX_BATCH, max_queue=1 << 20)
         st = srv.run_trace((tr.t * 1e9).astype(np.int64), hh, ww, tr.r, offs[pi], foffs, pool_dev, flt)
         srv.close()
         result["serve"] = {"requests": tr.n, "rate_req_s": args.serve_rate, "seconds": args.serve_seconds,
@@ -518,9 +523,10 @@ def main():
         log("serve: p50 %.1f us p99 %.1f us, %.3f Gpx/s, mean batch %.2f" % (st["p50_us"], st["p99_us"],
                                                                           st["gpx_per_s"], st["mean_batch"]))
         # Arrival-rate sweep up to saturation (about 100,000 requests at
-        # 2,000,000 req/s, about 600 Gpx/s offered, above what the GPU can
-        # drain): what continuous batching sustains as the load grows; the
-        # plain section above is the one-launch-per-image rate.
+        # 2,000,000 req/s, about 630 Gpx/s offered, and 200,000 at 4,000,000
+        # req/s, about 1,270 Gpx/s, both above what the GPU can drain): what
+        # continuous batching sustains as the load grows; the plain section
+        # above is the one-launch-per-image rate.
         def trace_filters(tr_):
             fls_, fo_ = [], np.zeros(tr_.n, np.int64)
             o_ = 0
@@ -532,11 +538,11 @@ def main():
             return np.concatenate(fls_), fo_
 
         sweep = []
-        for rate, secs, seed in ((2.0e4, 3.0, 8), (2.0e5, 0.5, 9), (2.0e6, 0.05, 7)):
+        for rate, secs, seed in ((2.0e4, 3.0, 8), (2.0e5, 0.5, 9), (2.0e6, 0.05, 7), (4.0e6, 0.05, 12)):
             tr_ = synth.arrival_trace(rate=rate, duration=secs, seed=seed)
             flt_, fo_ = trace_filters(tr_)
             pi_ = tr_.pool_index
-            srv = pf.Server(64 << 30, n_streams=4, max_batch=64, max_queue=1 << 20)
+            srv = pf.Server(64 << 30, n_streams=SERVE_STREAMS, max_batch=SERVE_MAX_BATCH, max_queue=1 << 20)
             ss = srv.run_trace((tr_.t * 1e9).astype(np.int64), pool.h[pi_], pool.w[pi_], tr_.r, offs[pi_], fo_,
                                pool_dev, flt_)
             srv.close()
@@ -548,9 +554,10 @@ def main():
                           "max_us": round(ss["max_us"], 1)})
             log("serve at %.0f req/s: %.1f Gpx/s, mean batch %.1f, p50 %.0f us p99 %.0f us" % (
                 rate, ss["gpx_per_s"], ss["mean_batch"], ss["p50_us"], ss["p99_us"]))
-        result["serve_sweep"] = {"points": sweep, "seeds": [8, 9, 7],
+        result["serve_sweep"] = {"points": sweep, "seeds": [8, 9, 7, 12], "n_streams": SERVE_STREAMS,
+                                 "max_batch": SERVE_MAX_BATCH,
                                  "workload": "open-loop Poisson arrivals at each rate, same pool and request mix; "
-                                             "the last point is past saturation"}
+                                             "the last two points are past saturation"}
         result["serve_saturation"] = dict(sweep[-1])
         # Upload mode: each request's image comes from host memory and is
         # copied into the server's arena at submit (PCIe-inclusive latency).
@@ -559,7 +566,7 @@ def main():
         flt_, fo_ = trace_filters(tr_)
         pi_ = tr_.pool_index
         host_pool = [pool.images[i] for i in range(pool.n)]
-        srv = pf.Server(64 << 30, n_streams=4, max_batch=64, max_queue=1 << 20)
+        srv = pf.Server(64 << 30, n_streams=SERVE_STREAMS, max_batch=SERVE_MAX_BATCH, max_queue=1 << 20)
         t_start = time.perf_counter_ns()
         tickets = []
         for i in range(tr_.n):

@@ -308,13 +308,14 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path);
  * tiles in flight ran fastest. Plans created earlier keep their grid. */
 pf_status pf_tune_batch_blocks(int32_t blocks_per_cu, int32_t *previous);
 /* Tune the PF_TUNE_BATCH entries for one batch (the arguments of
- * pf_batch_plan_create and pf_batch_plan_run): workgroups per compute unit
- * (1..4, see pf_tune_batch_blocks) first, then for each (kind, r, size
- * class) key the batch uses, row tiles of 8, 16, 32 and 64, timing
- * whole-batch launches on the device (median of 5 x `reps`) and keeping a
- * change only when the batch gets at least 3% faster. Single-image entries
- * are not touched. Installs the result and writes it to `path` if not
- * NULL. Overwrites `out`. */
+ * pf_batch_plan_create and pf_batch_plan_run), timing whole-batch launches
+ * on the device (median of 5 x `reps`): first a joint grid of workgroups
+ * per compute unit (1..4, see pf_tune_batch_blocks) x one row-tile height
+ * in {8, 16, 32, 64} for every key the batch uses, keeping the fastest
+ * point; then for each (kind, r, size class) key the batch uses, the other
+ * tile heights, keeping a change only when the batch gets at least 3%
+ * faster. Single-image entries are not touched. Installs the result and
+ * writes it to `path` if not NULL. Overwrites `out`. */
 pf_status pf_batch_autotune(int32_t n,
                             PF_ARR(const int32_t, h, n), PF_ARR(const int32_t, w, n),
                             PF_ARR(const int32_t, r, n), PF_ARR(const int32_t, kind, n),
@@ -372,7 +373,10 @@ pf_status pf_batch_plan_destroy(pf_batch_plan *plan);
  * admitted first-come first-served while their bytes fit in the budget;
  * admitted requests are packed into batches of at most `max_batch` requests
  * and launched on whichever stream is free, so new arrivals run while
- * earlier batches are still on the device. A request's result does not
+ * earlier batches are still on the device. While another batch is running,
+ * a launch waits up to 50 us (from its oldest request's arrival) for at
+ * least max_batch/2 admitted requests; with the device idle a request
+ * launches at once. A request's result does not
  * depend on which batch it lands in: filters as the single-image call with
  * the same variant, sums and histograms bit for bit as pf_sum_f32 and
  * pf_hist256_u8. Served filter radii: 0..PF_BATCH_R_MAX. */

@@ -630,7 +630,7 @@ class Server:
     current (or given) torch stream at submit, and this object keeps a
     reference to the tensor until its result is fetched or released."""
 
-    def __init__(self, hbm_budget_bytes: int, n_streams: int = 2, max_batch: int = 64, max_queue: int = 1 << 16,
+    def __init__(self, hbm_budget_bytes: int, n_streams: int = 3, max_batch: int = 256, max_queue: int = 1 << 16,
                  flags: int = 0):
         p = ctypes.c_void_p()
         _check(load().pf_server_create(int(hbm_budget_bytes), n_streams, max_batch, max_queue, flags,

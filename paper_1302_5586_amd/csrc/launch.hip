@@ -1,6 +1,7 @@
 // Radius dispatch for the single-image kernels, the uint8 kernels and the
 // batch kernels' entry points.
 #include <algorithm>
+#include <mutex>
 
 #include "filter_body.h"
 
@@ -48,13 +49,28 @@ void *batch_kernel_fn(int group, bool exact, int mask) {
 }
 
 int batch_grid_limit(int group, bool exact, int mask, int wpg) {
+    // Cached per (device, exact, mask, waves per group): the occupancy query
+    // is host work that every server batch would otherwise repeat.
+    static std::mutex mu;
+    static int cache[64][2][4][9] = {};
+    const int dev = std::min(std::max(dev_info().device, 0), 63);
+    const int m = std::min(std::max(mask, 0), 3), wq = std::min(std::max(wpg, 0), 8);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (group == 0 && cache[dev][exact][m][wq]) return cache[dev][exact][m][wq];
+    }
     int blocks = 0;
     void *fn = batch_kernel_fn(group, exact, mask);
     if (!fn ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, wpg * dev::kLanes, 0) != hipSuccess ||
         blocks < 1)
         blocks = 1;
-    return blocks * dev_info().cus;
+    const int limit = blocks * dev_info().cus;
+    if (group == 0) {
+        std::lock_guard<std::mutex> lk(mu);
+        cache[dev][exact][m][wq] = limit;
+    }
+    return limit;
 }
 
 int batch_grid(int group, bool exact, int mask, int wpg, int64_t ntiles) {

@@ -48,6 +48,11 @@ constexpr int kOpFilter = 0;  // request kinds besides PF_OP_SUM_F32, PF_OP_HIST
 // workspace.
 constexpr size_t kSlotBytes = 1 << 20;
 constexpr size_t kSlotWorkspace = 4 << 20;
+// While other batches are on the device, a launch waits up to this long
+// (from the oldest admitted request's arrival) for at least half a batch:
+// under load, batches fill instead of leaving with whatever arrived since
+// the last completion; with nothing in flight, a request launches at once.
+constexpr int64_t kHoldNs = 50000;
 
 int64_t round_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -144,6 +149,10 @@ struct pf_server {
 
     std::mutex mu;                     // guards everything below
     std::condition_variable cv_work;   // engine wakes on submit / stop
+    // Bumped (under `mu`) whenever the engine has new work: a submit, a
+    // release that frees arena bytes, shutdown. While batches are in flight
+    // the engine takes the lock only when this moved or an event completed.
+    std::atomic<int64_t> work_seq{0};
     std::condition_variable cv_done;   // waiters wake on completion
     std::deque<std::shared_ptr<Request>> queued;
     std::deque<std::shared_ptr<Request>> admitted;
@@ -167,6 +176,12 @@ namespace pf {
 namespace {
 
 // Release a finished request's arena bytes and ticket (lock held).
+// Tell the engine that it has new work (the caller holds s->mu).
+void wake_engine_locked(pf_server *s) {
+    s->work_seq.fetch_add(1, std::memory_order_release);
+    s->cv_work.notify_one();
+}
+
 void release_locked(pf_server *s, const std::shared_ptr<Request> &q) {
     if (q->out_off >= 0) s->arena.release(q->out_off, q->out_bytes);
     if (q->in_off >= 0) s->arena.release(q->in_off, q->in_bytes);
@@ -344,8 +359,31 @@ pf_status launch_slot(pf_server *s, Slot &sl) {
 
 void engine_main(pf_server *s) {
     (void)hipSetDevice(s->device);
-    std::unique_lock<std::mutex> lk(s->mu);
+    // Only this thread touches the slots once it runs, so their events are
+    // polled without the lock, and while batches run the lock is taken only
+    // when there is something to do: a submitter at a high request rate then
+    // finds it free instead of contending with a polling loop.
+    std::vector<hipError_t> polled(s->slots.size(), hipErrorNotReady);
+    std::unique_lock<std::mutex> lk(s->mu, std::defer_lock);
+    int64_t seen = -1;       // work_seq when the lock was last taken
+    int64_t hold_until = 0;  // a held launch is due by then (0: none)
+    bool again = true;       // the last pass changed state: look again
     for (;;) {
+        bool busy = false, finished = false;
+        for (size_t i = 0; i < s->slots.size(); ++i) {
+            polled[i] = hipErrorNotReady;
+            if (!s->slots[i].busy) continue;
+            busy = true;
+            polled[i] = hipEventQuery(s->slots[i].done);
+            finished |= polled[i] != hipErrorNotReady;
+        }
+        if (busy && !finished && !again && s->work_seq.load(std::memory_order_acquire) == seen &&
+            (hold_until == 0 || now_ns() < hold_until)) {
+            std::this_thread::yield();
+            continue;
+        }
+        lk.lock();
+        seen = s->work_seq.load(std::memory_order_relaxed);
         bool progressed = false;
         if (s->stop && !s->queued.empty()) {
             // Shutting down: requests not yet admitted fail (they may never
@@ -379,10 +417,10 @@ void engine_main(pf_server *s) {
         }
         // Completions.
         const int64_t t = now_ns();
-        for (Slot &sl : s->slots) {
-            if (!sl.busy) continue;
-            const hipError_t q = hipEventQuery(sl.done);
-            if (q == hipErrorNotReady) continue;
+        for (size_t i = 0; i < s->slots.size(); ++i) {
+            Slot &sl = s->slots[i];
+            const hipError_t q = polled[i];
+            if (!sl.busy || q == hipErrorNotReady) continue;
             for (auto &r : sl.reqs) {
                 r->t_done = t;
                 drop_event_locked(s, r);
@@ -405,7 +443,14 @@ void engine_main(pf_server *s) {
             s->cv_done.notify_all();
         }
         // Launch admitted requests on idle streams.
+        bool any_busy = false;
+        for (Slot &sl : s->slots) any_busy |= sl.busy;
+        const bool hold = any_busy && !s->stop && !s->admitted.empty() &&
+                          (int64_t)s->admitted.size() < std::max(1, s->max_batch / 2) &&
+                          now_ns() - s->admitted.front()->t_arrival < kHoldNs;
+        hold_until = hold ? s->admitted.front()->t_arrival + kHoldNs : 0;
         for (Slot &sl : s->slots) {
+            if (hold) break;
             if (sl.busy || s->admitted.empty()) continue;
             const size_t n = std::min<size_t>(s->admitted.size(), (size_t)s->max_batch);
             for (size_t i = 0; i < n; ++i) {
@@ -435,15 +480,10 @@ void engine_main(pf_server *s) {
         bool inflight = false;
         for (Slot &sl : s->slots) inflight |= sl.busy;
         if (s->stop && s->queued.empty() && s->admitted.empty() && !inflight) break;
-        if (progressed) continue;
-        if (inflight) {
-            // Poll for completions without holding the lock.
-            lk.unlock();
-            std::this_thread::yield();
-            lk.lock();
-        } else {
-            s->cv_work.wait_for(lk, std::chrono::milliseconds(50));
-        }
+        if (!progressed && !inflight) s->cv_work.wait_for(lk, std::chrono::milliseconds(50));
+        lk.unlock();
+        again = progressed || !inflight;
+        if (!progressed && inflight) std::this_thread::yield();
     }
 }
 
@@ -459,7 +499,7 @@ pf_status submit_locked(pf_server *s, std::shared_ptr<Request> q, int64_t *ticke
     s->first_arrival = std::min(s->first_arrival, q->t_arrival);
     s->queue_hw = std::max(s->queue_hw, (int64_t)s->queued.size());
     *ticket = q->ticket;
-    s->cv_work.notify_one();
+    wake_engine_locked(s);
     return PF_OK;
 }
 
@@ -564,7 +604,7 @@ pf_status copy_result(pf_server *s, int64_t ticket, int32_t op, int32_t h, int32
                                    out_is_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice);
     std::lock_guard<std::mutex> lk(s->mu);
     release_locked(s, q);
-    s->cv_work.notify_one();
+    wake_engine_locked(s);
     if (e != hipSuccess) return fail_hip(e, "result copy");
     return PF_OK;
 }
@@ -710,7 +750,7 @@ pf_status pf_server_release(pf_server *s, int64_t ticket) {
     if (pf_status st = lookup(s, ticket, &q)) return st;
     if (q->state != kDone && q->state != kFailed) return fail(PF_EAGAIN, "request not done");
     release_locked(s, q);
-    s->cv_work.notify_one();
+    wake_engine_locked(s);
     return PF_OK;
 }
 
@@ -756,24 +796,31 @@ pf_status pf_server_run_trace(pf_server *s, int32_t n, const int64_t *__restrict
         if (i && arrival_ns[i] < arrival_ns[i - 1]) return fail(PF_EINVAL, "arrival times must not decrease");
     }
     const int64_t t0 = now_ns();
-    for (int i = 0; i < n; ++i) {
-        const int64_t due = t0 + arrival_ns[i];
-        // Open loop: sleep until shortly before the scheduled time, then spin.
+    for (int i = 0; i < n;) {
+        // Open loop: sleep until shortly before the next scheduled time, then
+        // spin.
         for (;;) {
-            const int64_t left = due - now_ns();
+            const int64_t left = t0 + arrival_ns[i] - now_ns();
             if (left <= 0) break;
             if (left > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(left - 100000));
             else std::this_thread::yield();
         }
-        std::shared_ptr<Request> q;
+        // Everything already due goes in under one lock, each request with
+        // its own scheduled arrival time: one lock hand-off per group instead
+        // of per request when arrivals come faster than a submit.
+        const int64_t now = now_ns();
         std::lock_guard<std::mutex> lk(s->mu);
-        // The pool is complete before the call (documented): no ordering event.
-        pf_status st = make_request(s, h[i], w[i], r[i], PF_KIND_SEP, in + pix_off[i], 0, filt + filt_off[i], nullptr,
-                                    false, due, &q);
-        if (st) return st;
-        q->auto_release = true;
-        int64_t t;
-        if ((st = submit_locked(s, q, &t))) return st;
+        for (int g = 0; i < n && g < 256 && t0 + arrival_ns[i] <= now; ++i, ++g) {
+            std::shared_ptr<Request> q;
+            // The pool is complete before the call (documented): no ordering
+            // event.
+            pf_status st = make_request(s, h[i], w[i], r[i], PF_KIND_SEP, in + pix_off[i], 0, filt + filt_off[i],
+                                        nullptr, false, t0 + arrival_ns[i], &q);
+            if (st) return st;
+            q->auto_release = true;
+            int64_t t;
+            if ((st = submit_locked(s, q, &t))) return st;
+        }
     }
     std::unique_lock<std::mutex> lk(s->mu);
     s->cv_done.wait(lk, [&] { return s->completed + (s->dev_error != PF_OK) >= s->submitted || s->dev_error != PF_OK; });
@@ -810,7 +857,7 @@ pf_status pf_server_destroy(pf_server *s) {
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
-        s->cv_work.notify_all();
+        wake_engine_locked(s);
     }
     if (s->engine.joinable()) s->engine.join();
     for (Slot &sl : s->slots) {

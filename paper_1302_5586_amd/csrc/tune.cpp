@@ -377,11 +377,11 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
     if (he != hipSuccess) return fail_hip(he, "stream");
     std::vector<pf_tune_entry> out;
     pf_status st = PF_OK;
-    // One pair of buffers large enough for every class: 4 rotating sets of
-    // 4096 x 4096 floats (512 MiB touched per rotation, more than the 256 MB
-    // last-level cache holds).
+    // One pair of buffers large enough for every class: 8 rotating sets of
+    // 4096 x 4096 floats (1 GiB touched per rotation, four times what the
+    // 256 MB last-level cache holds, so timed reads come from HBM).
     const size_t big = (size_t)4096 * 4096;
-    const int nrot = 4;
+    const int nrot = 8;
     float *in = nullptr, *outb = nullptr, *filt = nullptr;
     if ((he = hipMalloc(&in, big * 4 * nrot)) != hipSuccess || (he = hipMalloc(&outb, big * 4 * nrot)) != hipSuccess ||
         (he = hipMalloc(&filt, 4096)) != hipSuccess) {
@@ -438,7 +438,7 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
                                 return launch_u8(r, (const uint8_t *)in + o, (const int8_t *)filt, (uint8_t *)outb + o,
                                                  3, h, w, 6, by, wpg, s);
                             },
-                            nb1, reps, 3, s, us);
+                            nb1, reps, 5, s, us);
                     }
                     return time_launch(
                         [&](int i) {
@@ -446,7 +446,7 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
                             return launch_f32(r, v, false, in + o, filt, filt + (2 * r + 1), outb + o, h, w, by, wpg,
                                               s);
                         },
-                        nb1, reps, 3, s, us);
+                        nb1, reps, 5, s, us);
                 };
                 for (const auto &shape : shapes) {
                     float us = 0.0f;
@@ -541,29 +541,42 @@ pf_status pf_batch_autotune(int32_t n, const int32_t *__restrict h, const int32_
         }
         std::sort(keys.begin(), keys.end());
     }
-    float best = 0.0f;
-    pf_status st = measure(&best);
-    // Workgroups per compute unit first (the whole batch moves together).
+    // A joint grid first: workgroups per compute unit x one tile height for
+    // every key the batch uses (the two interact: the grid sets how many
+    // tiles are in flight, the tile height how many tiles there are). The
+    // best point is kept outright.
+    auto set_all = [&](int by) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (const auto &k : keys) g_table.e[PF_TUNE_BATCH][k[0]][k[1]][k[2]].rows_per_wave = by;
+    };
+    float best = INFINITY;
+    int best_bpc = 1, best_by = 16;
+    pf_status st = PF_OK;
     for (int bpc = 1; bpc <= 4 && st == PF_OK; ++bpc) {
-        int keep = 0;
-        {
-            std::lock_guard<std::mutex> lk(g_mu);
-            keep = g_table.batch_blocks_per_cu;
-            if (bpc == keep) continue;
-            g_table.batch_blocks_per_cu = bpc;
-        }
-        float us = 0.0f;
-        st = measure(&us);
-        if (st == PF_OK && us < 0.97f * best) {
-            best = us;
-        } else {
-            std::lock_guard<std::mutex> lk(g_mu);
-            g_table.batch_blocks_per_cu = keep;
+        for (int by : {8, 16, 32, 64}) {
+            {
+                std::lock_guard<std::mutex> lk(g_mu);
+                g_table.batch_blocks_per_cu = bpc;
+            }
+            set_all(by);
+            float us = 0.0f;
+            st = measure(&us);
+            if (st != PF_OK) break;
+            if (us < best) {
+                best = us;
+                best_bpc = bpc;
+                best_by = by;
+            }
         }
     }
-    // Coordinate descent over the batch-context keys the batch uses, one key
-    // at a time: a new tile height is kept only when the whole batch gets at
-    // least 3% faster. Single-image entries are not touched.
+    if (st == PF_OK) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_table.batch_blocks_per_cu = best_bpc;
+    }
+    set_all(best_by);
+    // Then coordinate descent over the batch-context keys the batch uses, one
+    // key at a time: a new tile height is kept only when the whole batch gets
+    // at least 3% faster. Single-image entries are not touched.
     const int bys[] = {8, 16, 32, 64};
     for (const auto &k : keys) {
         if (st != PF_OK) break;
