@@ -69,7 +69,7 @@ def parse():
                     help="tune the table (per class, then on the batch workload), write it to this path, and "
                          "bench with it")
     ap.add_argument("--skip", default="",
-                    help="comma list of sections to skip: exact,plain,large,chain,reduce,inc,small,rgb,serve,cpu")
+                    help="comma list of sections to skip: probes,exact,plain,large,chain,reduce,inc,small,rgb,serve,cpu")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 512 MiB device copy 4 times (reference for counter scaling)")
     return ap.parse_args()
@@ -292,6 +292,43 @@ def main():
             msg, pg, value / pg))
         del g
 
+    # ---- probes: what plain kernels sustain on this device ---------------------
+    # An ALU rate (one instruction back to back on independent registers) and
+    # a flat HBM copy of the 4096x4096 image's bytes: the filters' timings
+    # are read against these as well as against the published peaks.
+    probes = {}
+    if "probes" not in skip:
+        pbuf = torch.empty(4096 * 256, dtype=torch.int32, device=dev)
+        for pname, op in (("dot4", pf.PROBE_DOT4), ("fma", pf.PROBE_FMA)):
+            ops = pf.probe_alu(op, 4096, 200, pbuf)
+            ms = time_events(torch, lambda i: pf.probe_alu(op, 4096, 200, pbuf), 5, stream)
+            probes[pname + "_lane_ops_per_s"] = ops / (ms * 1e-3)
+            log("probe %s: %.2f T lane-ops/s (%.3f of 256 CUs x 64 lanes x 2.4 GHz)" % (
+                pname, ops / (ms * 1e-3) / 1e12, ops / (ms * 1e-3) / VALU_LANE_OPS))
+        del pbuf
+        n = 4096 * 4096
+        nbuf = 8
+        xs = [torch.ones(n, dtype=torch.float32, device=dev) for _ in range(nbuf)]
+        os_ = [torch.empty_like(xs[0]) for _ in range(nbuf)]
+        for i in range(nbuf):
+            pf.probe_copy(xs[i], os_[i])
+        ms = time_events(torch, lambda i: pf.probe_copy(xs[i % nbuf], os_[i % nbuf]), 64, stream)
+        probes["copy_4096sq_us"] = ms * 1e3
+        probes["copy_GBs"] = 8 * n / (ms * 1e-3) / 1e9
+        log("probe copy 4096x4096 FP32: %.2f us, %.0f GB/s (%.3f of HBM)" % (
+            ms * 1e3, probes["copy_GBs"], probes["copy_GBs"] / HBM_PEAK_GBS))
+        del xs, os_
+        result["probes"] = {
+            "dot4_T_lane_ops_per_s": round(probes["dot4_lane_ops_per_s"] / 1e12, 2),
+            "dot4_frac_of_derived_peak": round(probes["dot4_lane_ops_per_s"] / VALU_LANE_OPS, 4),
+            "fma_T_lane_ops_per_s": round(probes["fma_lane_ops_per_s"] / 1e12, 2),
+            "fma_frac_of_derived_peak": round(probes["fma_lane_ops_per_s"] / VALU_LANE_OPS, 4),
+            "copy_4096sq_us": round(probes["copy_4096sq_us"], 2),
+            "copy_GBs": round(probes["copy_GBs"], 1),
+            "copy_frac_hbm": round(probes["copy_GBs"] / HBM_PEAK_GBS, 4),
+            "workload": "4096 workgroups x 256 lanes x 200 x 128 instructions on 8 independent registers; flat "
+                        "non-temporal copy of 4096x4096 FP32, buffers rotated over 1 GiB"}
+
     # ---- 4096x4096 5x5 Gaussian, plain filter ---------------------------------
     if "large" not in skip:
         cfg = synth.config_large()
@@ -315,6 +352,9 @@ def main():
                             "achieved_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
                             "workload": "4096x4096 FP32, 5x5 Gaussian sigma 1.5, seed 1, buffers rotated over 1 GiB"
                                         + ("; PF_FLAG_EXACT" if name.endswith("exact") else "")}
+            if "copy_4096sq_us" in probes:
+                # the copy probe moves the same 8 bytes per pixel
+                result[name]["frac_of_copy_probe"] = round(probes["copy_4096sq_us"] / (ms * 1e3), 4)
             if name.endswith("exact"):
                 base = result[name[:-len("_exact")]]["us_per_call"]
                 result[name]["cost_vs_default"] = round(ms * 1e3 / base, 3)
@@ -479,6 +519,8 @@ def main():
                             "achieved_GBs": round(2 * npx / (ms * 1e-3) / 1e9, 1),
                             "dot4_lane_ops_per_s": round(dot4 / (ms * 1e-3) / 1e12, 3),
                             "frac_alu_dot4": round(dot4 / (ms * 1e-3) / VALU_LANE_OPS, 4),
+                            "frac_of_dot4_probe": (round(dot4 / (ms * 1e-3) / probes["dot4_lane_ops_per_s"], 4)
+                                                   if "dot4_lane_ops_per_s" in probes else None),
                             "workload": "3x1080x1920 uint8 planar, 7x7 int8 weights in -8..8, shift 6, seed 2"}
         log("rgb_u8: %.2f us/call" % (ms * 1e3))
 

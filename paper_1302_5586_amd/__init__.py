@@ -111,6 +111,8 @@ _SIGS = {
     "pf_edge_inc_atomic_f64": (_I32, [_I32, _I32, _P, _P, _P, _P]),
     "pf_sum_f32": (_I32, [_I64, _P, _P, _P, ctypes.c_size_t, _P]),
     "pf_sum_f32_noalloc": (_I32, [_I64, _P, _P, _P]),
+    "pf_probe_alu": (_I32, [_I32, _I32, _I32, _P, _P]),
+    "pf_probe_copy": (_I32, [_I64, _P, _P, _P]),
     "pf_hist_workspace": (_I32, [_I64, _P]),
     "pf_hist256_u8": (_I32, [_I64, _P, _P, _P, ctypes.c_size_t, _P]),
     "pf_filter_chain_f32": (_I32, [_I32, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
@@ -304,6 +306,32 @@ def sum_f32_noalloc(x, *, out=None, stream=None):
     if out is None:
         out = torch.empty(2, dtype=torch.float64, device=x.device)
     _check(load().pf_sum_f32_noalloc(x.numel(), x.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+PROBE_DOT4 = 0
+PROBE_FMA = 1
+
+
+def probe_alu(op: int, blocks: int, iters: int, out, stream=None) -> int:
+    """Launch the ALU-rate probe (``PROBE_DOT4`` or ``PROBE_FMA``) into a
+    CUDA int32/float32 tensor of ``blocks * 256`` elements; returns the
+    lane-instructions of the launch."""
+    if not out.is_cuda or out.numel() < blocks * 256 or out.element_size() != 4:
+        raise ValueError("out must be a CUDA tensor of blocks * 256 4-byte values")
+    _check(load().pf_probe_alu(op, blocks, iters, out.data_ptr(), _stream_ptr(stream)))
+    return blocks * 256 * iters * 128
+
+
+def probe_copy(x, out, stream=None):
+    """The HBM copy probe: out[:] = x (contiguous CUDA float32 tensors)."""
+    torch = _torch()
+    for t in (x, out):
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError("x and out must be contiguous CUDA float32 tensors")
+    if out.numel() != x.numel():
+        raise ValueError("x and out differ in size")
+    _check(load().pf_probe_copy(x.numel(), x.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
     return out
 
 

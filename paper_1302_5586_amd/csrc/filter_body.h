@@ -43,6 +43,7 @@
 // XCD (xcd_remap).
 #pragma once
 
+#include <algorithm>
 #include <type_traits>
 
 #include "dev_common.h"
@@ -852,11 +853,12 @@ __device__ __forceinline__ void strip_u8(const uint8_t *__restrict__ in, const i
         rows_u8<R, kTiny>(wt, in, out, acc, h, w, shift, xs, y0, rows, out_lane);
 }
 
+// Wave tile (sx, sy) of a plane covers rows [sy h / strips_y, (sy+1) h /
+// strips_y): the rows are spread evenly over the tiles of a strip column.
 template <int R>
 __global__ __launch_bounds__(512) void k_filter_u8(const uint8_t *__restrict__ in, const int8_t *__restrict__ filt,
                                                    uint8_t *__restrict__ out, int h, int w, int shift, int aligned,
-                                                   int by, int strips_x, int strips_y, int tasks_per_plane,
-                                                   int ntasks) {
+                                                   int strips_x, int strips_y, int tasks_per_plane, int ntasks) {
     const int wpg = blockDim.x / kLanes;
     const int wave = uniform(threadIdx.x / kLanes);
     const int lane = threadIdx.x % kLanes;
@@ -866,10 +868,10 @@ __global__ __launch_bounds__(512) void k_filter_u8(const uint8_t *__restrict__ i
     const int local = t - p * tasks_per_plane;
     int sx, sy;
     tile_xy<PF_U8_COLMAJOR != 0>(local, strips_x, strips_y, sx, sy);
-    const int y0 = sy * by;
+    const int y0 = (int)((int64_t)sy * h / strips_y);
+    const int y1 = (int)((int64_t)(sy + 1) * h / strips_y);
     const int64_t plane = (int64_t)p * h * w;
-    strip_u8<R>(in + plane, filt, out + plane, h, w, shift, aligned != 0, sx * strip_width_u8(R), y0,
-                min(by, h - y0), lane);
+    strip_u8<R>(in + plane, filt, out + plane, h, w, shift, aligned != 0, sx * strip_width_u8(R), y0, y1 - y0, lane);
 }
 
 }  // namespace dev
@@ -915,7 +917,17 @@ template <int R>
 hipError_t launch_u8_t(const uint8_t *in, const int8_t *filt, uint8_t *out, int c, int h, int w, int shift, int by,
                        int wpg, hipStream_t s) {
     const int sw = strip_width_u8(R);
-    const int strips_x = cdiv(w, sw), strips_y = cdiv(h, by);
+    const int strips_x = cdiv(w, sw);
+    // The uint8 kernel is ALU-bound: its time is the number of rounds of
+    // waves a SIMD runs times the rows a wave folds. Keep the rounds that
+    // `by` asks for, but cut each strip column into as many tiles as fill
+    // those rounds (rows spread evenly, never more than `by` per tile), so
+    // the last round is not left partly idle.
+    const int64_t cols = (int64_t)strips_x * c;
+    const int64_t simds = 4 * (int64_t)std::max(dev_info().cus, 1);
+    const int64_t asked = cdiv(h, by);
+    const int64_t rounds = (cols * asked + simds - 1) / simds;
+    const int64_t strips_y = std::min<int64_t>(h, std::max<int64_t>(asked, rounds * simds / cols));
     const int64_t per_plane = (int64_t)strips_x * strips_y;
     const int64_t ntasks64 = per_plane * c;
     if (ntasks64 > INT32_MAX) return hipErrorInvalidValue;
@@ -923,7 +935,7 @@ hipError_t launch_u8_t(const uint8_t *in, const int8_t *filt, uint8_t *out, int 
     const int grid = cdiv(ntasks, wpg);
     const int aligned = (w % 4 == 0) && ((uintptr_t)in % 4 == 0) && ((uintptr_t)out % 4 == 0);
     hipLaunchKernelGGL((k_filter_u8<R>), dim3(grid), dim3(wpg * kLanes), 0, s, in, filt, out, h, w, shift, aligned,
-                       by, strips_x, strips_y, (int)per_plane, ntasks);
+                       strips_x, (int)strips_y, (int)per_plane, ntasks);
     return hipGetLastError();
 }
 

@@ -23,8 +23,11 @@ namespace pf {
 #ifndef PF_STRIP_ALIGNED
 #define PF_STRIP_ALIGNED 1
 #endif
+#ifndef PF_STRIP_ALIGNED_RMAX
+#define PF_STRIP_ALIGNED_RMAX 2
+#endif
 constexpr int halo_lanes(int r) { return (r + 3) / 4; }
-constexpr bool aligned_strip(int r) { return PF_STRIP_ALIGNED && r >= 1 && r <= 2; }
+constexpr bool aligned_strip(int r) { return PF_STRIP_ALIGNED && r >= 1 && r <= PF_STRIP_ALIGNED_RMAX; }
 constexpr int idle_lanes(int r) { return aligned_strip(r) ? 0 : halo_lanes(r); }
 constexpr int strip_width(int r) { return 4 * (64 - 2 * idle_lanes(r)); }
 // The uint8 strip keeps its halo lanes at every radius.
