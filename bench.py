@@ -76,8 +76,8 @@ def parse():
 
 
 KERNEL_SOURCES = ("paper_1302_5586_amd/csrc/filter_body.h", "paper_1302_5586_amd/csrc/pf_internal.h",
-                  "paper_1302_5586_amd/csrc/batch_inst.hip", "paper_1302_5586_amd/csrc/f32_inst.hip",
-                  "paper_1302_5586_amd/csrc/launch.hip")
+                  "paper_1302_5586_amd/csrc/dev_common.h", "paper_1302_5586_amd/csrc/batch_inst.hip",
+                  "paper_1302_5586_amd/csrc/f32_inst.hip", "paper_1302_5586_amd/csrc/launch.hip")
 
 
 def kernel_source_hash():
@@ -634,6 +634,56 @@ def main():
                                               "(copied host to device inside the request; latency measured from "
                                               "submit)"}
         log("serve upload: p50 %.1f us p99 %.1f us" % (su["p50_us"], su["p99_us"]))
+        # Mixed kinds: filters beside sum/mean and histogram requests on the
+        # same server (the reductions batched with the filters), inputs
+        # device-resident, latency measured from submit.
+        mix_secs = min(5.0, args.serve_seconds)
+        tr_ = synth.arrival_trace(rate=args.serve_rate, duration=mix_secs, seed=13)
+        flt_, fo_ = trace_filters(tr_)
+        pi_ = tr_.pool_index
+        kinds = np.random.default_rng(14).choice(3, size=tr_.n, p=[0.6, 0.2, 0.2])
+        gu = torch.Generator(device=dev).manual_seed(15)
+        pool_u8 = torch.randint(0, 256, (int(offs[-1] + pool.h[-1] * pool.w[-1]),), dtype=torch.uint8, device=dev,
+                                generator=gu)
+        torch.cuda.synchronize()
+        srv = pf.Server(64 << 30, n_streams=SERVE_STREAMS, max_batch=SERVE_MAX_BATCH, max_queue=1 << 20)
+        t_start = time.perf_counter_ns()
+        tickets = []
+        for i in range(tr_.n):
+            due = t_start + int(tr_.t[i] * 1e9)
+            while time.perf_counter_ns() < due:
+                pass
+            j = int(pi_[i])
+            o, hh_, ww_ = int(offs[j]), int(pool.h[j]), int(pool.w[j])
+            if kinds[i] == 0:
+                k = 2 * int(tr_.r[i]) + 1
+                tk = srv.submit(pool_dev[o:o + hh_ * ww_].view(hh_, ww_), int(tr_.r[i]), pf.KIND_SEP,
+                                flt_[fo_[i]:fo_[i] + 2 * k])
+            elif kinds[i] == 1:
+                tk = srv.submit_sum(pool_dev[o:o + hh_ * ww_])
+            else:
+                tk = srv.submit_hist(pool_u8[o:o + hh_ * ww_])
+            tickets.append(tk)
+            while len(tickets) > 256 and srv.poll(tickets[0]):
+                srv.release(tickets.pop(0))
+        for t in tickets:
+            srv.wait(t)
+            srv.release(t)
+        sm = srv.stats()
+        srv.close()
+        del pool_u8
+        result["serve_mixed"] = {"requests": tr_.n, "filters": int((kinds == 0).sum()), "sums": int((kinds == 1).sum()),
+                                 "histograms": int((kinds == 2).sum()), "rate_req_s": args.serve_rate,
+                                 "seconds": mix_secs, "p50_us": round(sm["p50_us"], 1),
+                                 "p99_us": round(sm["p99_us"], 1), "max_us": round(sm["max_us"], 1),
+                                 "filter_gpx_per_s": round(sm["gpx_per_s"], 4), "batches": sm["batches"],
+                                 "mean_batch": round(sm["mean_batch"], 2),
+                                 "workload": "Poisson arrivals (seed 13), 60% separable filters / 20% float64 "
+                                             "sum+mean of an FP32 pool image / 20% 256-bin histogram of a uint8 "
+                                             "image of the same size (seed 15); device-resident inputs; latency "
+                                             "from submit"}
+        log("serve mixed: p50 %.1f us p99 %.1f us, mean batch %.2f" % (sm["p50_us"], sm["p99_us"],
+                                                                     sm["mean_batch"]))
 
     # ---- CPU baseline: the oracle on one core and on all host cores -----------
     if "cpu" not in skip:
