@@ -89,6 +89,9 @@ typedef int32_t pf_status;
 #define PF_VAR_DIRECT      0  /* full 2D taps                                     */
 #define PF_VAR_SEPARABLE   1  /* fused row pass + column pass (PF_KIND_SEP only)  */
 #define PF_VAR_SEP_DIRECT  2  /* PF_KIND_SEP run as 2D taps fy[i]*fx[j] (FP32)    */
+/* Largest radius PF_VAR_SEP_DIRECT runs at: above it the (2r+1)^2 computed
+ * taps no longer fit in registers (PF_EUNSUPPORTED). */
+#define PF_SEP_DIRECT_R_MAX 5
 
 /* Border rules: the value an index outside [0, n) of an axis reads. */
 #define PF_BORDER_CLAMP    0  /* nearest edge element: a a | a b c | c c           */

@@ -27,6 +27,7 @@ LIB_PATH = os.environ.get("PENCILFILTER_LIB") or os.path.join(_HERE, "libpencilf
 PF_OK, PF_EINVAL, PF_EALIAS, PF_EUNSUPPORTED, PF_EDEVICE, PF_ENOMEM, PF_EBUDGET, PF_EAGAIN, PF_ETIMEDOUT = range(9)
 PF_R_MAX = 8
 PF_BATCH_R_MAX = 4
+PF_SEP_DIRECT_R_MAX = 5
 FLAG_EXACT = 0x1
 BATCH_GRAPH = 0x2
 BATCH_NO_TUNE = 0x4

@@ -261,6 +261,8 @@ pf_status pf_filter_f32_shaped(int32_t h, int32_t w, int32_t r, int32_t kind, in
     if (variant < PF_VAR_DIRECT || variant > PF_VAR_SEP_DIRECT) return fail(PF_EINVAL, "unknown variant");
     if (kind == PF_KIND_2D && variant != PF_VAR_DIRECT) return fail(PF_EINVAL, "a 2D filter runs only as PF_VAR_DIRECT");
     if (kind == PF_KIND_SEP && variant == PF_VAR_DIRECT) variant = PF_VAR_SEP_DIRECT;
+    if (variant == PF_VAR_SEP_DIRECT && r > PF_SEP_DIRECT_R_MAX)
+        return fail(PF_EUNSUPPORTED, "PF_VAR_SEP_DIRECT runs radii 0.." + std::to_string(PF_SEP_DIRECT_R_MAX));
     if (!valid_shape(rows_per_wave, waves_per_group)) return fail(PF_EINVAL, "unsupported launch shape");
     const float *fb = (kind == PF_KIND_SEP && filt) ? filt + (2 * r + 1) : nullptr;
     return run_f32(h, w, r, kind, variant, rows_per_wave, waves_per_group, in, filt, fb, out, flags, stream);

@@ -907,7 +907,11 @@ hipError_t launch_f32_v(int var, const float *in, const float *fa, const float *
         case PF_VAR_SEPARABLE:
             return launch_f32_t<R, PF_VAR_SEPARABLE, EXACT>(in, fa, fb, out, h, w, by, wpg, s);
         case PF_VAR_SEP_DIRECT:
-            return launch_f32_t<R, PF_VAR_SEP_DIRECT, EXACT>(in, fa, fb, out, h, w, by, wpg, s);
+            // Not built above PF_SEP_DIRECT_R_MAX (its taps would spill).
+            if constexpr (R <= PF_SEP_DIRECT_R_MAX)
+                return launch_f32_t<R, PF_VAR_SEP_DIRECT, EXACT>(in, fa, fb, out, h, w, by, wpg, s);
+            else
+                return hipErrorInvalidValue;
         default:
             return hipErrorInvalidValue;
     }

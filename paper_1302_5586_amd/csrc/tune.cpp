@@ -81,7 +81,8 @@ bool entry_ok(const pf_tune_entry &e) {
         return e.variant == (e.kind == PF_KIND_SEP ? PF_VAR_SEPARABLE : PF_VAR_DIRECT);
     }
     // A separable filter called alone may also run as 2D taps fy[i] * fx[j].
-    if (e.kind == PF_KIND_SEP) return e.variant == PF_VAR_SEPARABLE || e.variant == PF_VAR_SEP_DIRECT;
+    if (e.kind == PF_KIND_SEP)
+        return e.variant == PF_VAR_SEPARABLE || (e.variant == PF_VAR_SEP_DIRECT && e.r <= PF_SEP_DIRECT_R_MAX);
     return e.variant == PF_VAR_DIRECT;
 }
 
@@ -460,7 +461,7 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
                     }
                 }
                 // The variant axis: a separable filter may run as 2D taps.
-                if (st == PF_OK && kind == PF_KIND_SEP) {
+                if (st == PF_OK && kind == PF_KIND_SEP && r <= PF_SEP_DIRECT_R_MAX) {
                     float us = 0.0f;
                     st = time_single(PF_VAR_SEP_DIRECT, best.rows_per_wave, best.waves_per_group, &us);
                     if (st == PF_OK && better(us, best)) {

@@ -78,6 +78,9 @@ def test_filter_flags_and_filter_alias(lib):
                                     FAKE + (1 << 20), 0, None) == pf.PF_EINVAL
     assert lib.pf_filter_f32_shaped(4, 4, 1, pf.KIND_2D, pf.VAR_DIRECT, 132, 4, FAKE, FAKE + 4096,
                                     FAKE + (1 << 20), 0, None) == pf.PF_EINVAL
+    # separable filters run as 2D taps up to radius 5 only
+    assert lib.pf_filter_f32_shaped(40, 40, 6, pf.KIND_SEP, pf.VAR_SEP_DIRECT, 16, 4, FAKE, FAKE + 65536,
+                                    FAKE + (1 << 20), 0, None) == pf.PF_EUNSUPPORTED
 
 
 def test_u8_validation(lib):
@@ -132,6 +135,9 @@ def test_tune_table_roundtrip(lib, tmp_path):
     with pytest.raises(pf.PFInvalid):   # batches never run separable filters as 2D taps
         pf.tune_set([pf.TuneEntry(kind=pf.KIND_SEP, r=3, size_class=0, variant=pf.VAR_SEP_DIRECT,
                                   rows_per_wave=16, waves_per_group=4, context=pf.TUNE_BATCH)])
+    with pytest.raises(pf.PFInvalid):   # 2D taps of a separable filter: radii 0..5
+        pf.tune_set([pf.TuneEntry(kind=pf.KIND_SEP, r=6, size_class=0, variant=pf.VAR_SEP_DIRECT,
+                                  rows_per_wave=16, waves_per_group=4, context=pf.TUNE_SINGLE)])
     with pytest.raises(pf.PFInvalid):   # batch kernels run four waves per workgroup
         pf.tune_set([pf.TuneEntry(kind=pf.KIND_SEP, r=3, size_class=0, variant=pf.VAR_SEPARABLE,
                                   rows_per_wave=16, waves_per_group=2, context=pf.TUNE_BATCH)])

@@ -58,7 +58,7 @@ def test_separable_all_radii(r):
         assert np.array_equal(exact, ref), "exact sep r=%d %dx%d differs from the oracle" % (r, h, w)
 
 
-@pytest.mark.parametrize("r", [0, 1, 2])
+@pytest.mark.parametrize("r", [0, 1, 2, 4, 5])
 def test_separable_as_direct(r):
     dev = device()
     rng = np.random.default_rng(3000 + r)
