@@ -295,12 +295,14 @@ pf_status pf_tune_reset(void);
 /* Load / save the table as JSON text (host file path). */
 pf_status pf_tune_load(const char *path);
 pf_status pf_tune_save(const char *path);
-/* Measure, on the current device with hipEvents (median of `reps` timed
- * runs over rotated buffers), for r in 0..r_max and the three size
+/* Measure, on the current device with hipEvents (median of 5 groups of
+ * `reps` timed runs over buffers rotated through 1 GiB), for r in 0..r_max
+ * and the three size
  * classes: every (rows_per_wave in {8, 16, 32, 64}, for PF_KIND_U8 also
  * 12, 20, 24 and 48) x (waves_per_group in {1, 2, 4, 8}) shape of
  * single-image calls of every kind, and for
- * PF_KIND_SEP also the PF_VAR_SEP_DIRECT variant at the best shape; and the
+ * PF_KIND_SEP (r <= PF_SEP_DIRECT_R_MAX) also the PF_VAR_SEP_DIRECT variant
+ * at the best shape; and the
  * tile heights {8, 16, 32, 64} of the batch kernel on a batch of class
  * images (FP32 kinds). A candidate replaces the default only when at least
  * 3% faster. Installs the winners and writes the table to `path` if it is
