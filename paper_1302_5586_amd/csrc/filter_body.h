@@ -542,6 +542,10 @@ __device__ __forceinline__ void strip_f32(const float *__restrict__ in, const fl
 #ifndef PF_U8_COLMAJOR
 #define PF_U8_COLMAJOR 1
 #endif
+// Rows per pipelined uint8 chunk: a multiple of K near this many.
+#ifndef PF_U8_CHUNK
+#define PF_U8_CHUNK 8
+#endif
 template <bool COLMAJOR = kTileColMajorF32>
 __device__ __forceinline__ void tile_xy(int t, int strips_x, int strips_y, int &sx, int &sy) {
     tile_strip(COLMAJOR, t, strips_x, strips_y, sx, sy);
@@ -793,7 +797,7 @@ __device__ __forceinline__ void rows_u8(const WeightsU8<R> &wt, const uint8_t *_
                                         uint8_t *__restrict__ out, int (&acc)[2 * R + 1][4], int h, int w, int shift,
                                         int xs, int y0, int rows, bool out_lane) {
     constexpr int K = 2 * R + 1;
-    constexpr int CH = K * (K >= 8 ? 1 : 8 / K);
+    constexpr int CH = K * (PF_U8_CHUNK / K > 0 ? PF_U8_CHUNK / K : 1);
     const int nin = rows + 2 * R;
     int i0 = 2 * R;
     if (i0 + CH <= nin) {

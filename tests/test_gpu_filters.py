@@ -193,3 +193,29 @@ def test_u8_tile_shapes_bit_exact(by, wpg):
     finally:
         pf.tune_reset()
     assert np.array_equal(got, ref)
+
+
+# Multi-plane and tall images under workgroups of 2, 4 and 8 waves: groups
+# that straddle strip columns and planes, and (wpg 8) waves without a tile.
+GROUP_IMAGES = [(3, 1080, 1920), (2, 2000, 1000), (1, 1400, 1000)]
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_u8_group_shapes_bit_exact(r):
+    dev = device()
+    rng = np.random.default_rng(4100 + r)
+    for (c, h, w) in GROUP_IMAGES:
+        img = rng.integers(0, 256, (c, h, w), dtype=np.uint8)
+        f = rng.integers(-8, 9, (2 * r + 1, 2 * r + 1)).astype(np.int8)
+        ref = oracle.filter2d_u8(img, f, 6)
+        x, fd = _t(img, dev), _t(f, dev)
+        for by, wpg in ((16, 2), (16, 4), (12, 8), (24, 4)):
+            es = [pf.TuneEntry(kind=pf.KIND_U8, r=r, size_class=sc, variant=pf.VAR_DIRECT, rows_per_wave=by,
+                               waves_per_group=wpg, us=0.0, context=pf.TUNE_SINGLE) for sc in range(3)]
+            try:
+                pf.tune_set(es)
+                got = pf.filter2d_u8(x, fd, 6).cpu().numpy()
+            finally:
+                pf.tune_reset()
+            bad = int((got != ref).sum())
+            assert bad == 0, "u8 r=%d %dx%dx%d by=%d wpg=%d: %d bytes differ" % (r, c, h, w, by, wpg, bad)
