@@ -620,6 +620,11 @@ struct WeightsU8 {
     static constexpr int PAD = 4 * ND - K;  // zero taps in front of each row
     int32_t wd[K][ND];
     int32_t bias;  // 128 * sum of weights
+    // Byte selector (v_perm_b32) that turns the dword a lane loads into its
+    // 4 clamped pixels; set per strip (see load_u8). Applied where a row is
+    // folded, not where it is loaded, so that the load of the next chunk is
+    // not waited for early.
+    uint32_t sel = 0x03020100u;
 
     __device__ __forceinline__ explicit WeightsU8(const int8_t *__restrict__ filt) {
         int s = 0;
@@ -644,28 +649,41 @@ struct WeightsU8 {
     }
 };
 
-// Bytes xs .. xs+3 of a row, clamped to [0, w-1], packed little-endian.
-// kFast (rows 4-byte aligned, every lane's bytes end inside the row): one
-// dword load, the halo lane left of byte 0 replicating byte 0. kEdge
-// (aligned rows, w >= 4): the nearest in-bounds dword, bytes picked from
-// it. kTiny (unaligned rows or w < 4): one clamped byte load per byte.
+// The dword a lane loads for bytes xs .. xs+3 of a row; the byte selector
+// of load_sel_u8 turns it into those bytes clamped to [0, w-1], packed
+// little-endian. kFast (rows 4-byte aligned, every lane's bytes end inside
+// the row): the dword at xs (at 0 for the halo lane left of byte 0, which
+// replicates byte 0). kEdge (aligned rows, w >= 4): the nearest in-bounds
+// dword. kTiny (unaligned rows or w < 4): one clamped byte load per byte,
+// already in place.
 template <int MODE>
 __device__ __forceinline__ uint32_t load_u8(const uint8_t *__restrict__ row, int xs, int w) {
     if constexpr (MODE == kFast) {
-        const uint32_t t = ld(reinterpret_cast<const uint32_t *>(row + max(xs, 0)));
-        return xs < 0 ? (t & 0xffu) * 0x01010101u : t;
+        return ld(reinterpret_cast<const uint32_t *>(row + max(xs, 0)));
     } else if constexpr (MODE == kEdge) {
-        const int xa = clampi(xs, 0, w - 4);
-        const uint32_t t = ld(reinterpret_cast<const uint32_t *>(row + xa));
-        uint32_t v = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v |= ((t >> (8 * (clampi(xs + k, 0, w - 1) - xa))) & 0xffu) << (8 * k);
-        return v;
+        return ld(reinterpret_cast<const uint32_t *>(row + clampi(xs, 0, w - 4)));
     } else {
         uint32_t v = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) v |= (uint32_t)row[clampi(xs + k, 0, w - 1)] << (8 * k);
         return v;
+    }
+}
+
+// Byte selector for load_u8's dword in mode MODE (v_perm_b32 byte k = the
+// index, within that dword, of clamped byte xs + k).
+template <int MODE>
+__device__ __forceinline__ uint32_t load_sel_u8(int xs, int w) {
+    if constexpr (MODE == kFast) {
+        return xs < 0 ? 0u : 0x03020100u;
+    } else if constexpr (MODE == kEdge) {
+        const int xa = clampi(xs, 0, w - 4);
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s |= (uint32_t)(clampi(xs + k, 0, w - 1) - xa) << (8 * k);
+        return s;
+    } else {
+        return 0x03020100u;
     }
 }
 
@@ -676,7 +694,7 @@ __device__ __forceinline__ void fold_row_u8(const WeightsU8<R> &wt, uint32_t own
     constexpr int ND = WeightsU8<R>::ND;
     constexpr int PAD = WeightsU8<R>::PAD;
     uint32_t win[2 * NB + 1];
-    win[NB] = own ^ 0x80808080u;  // p - 128 as signed bytes
+    win[NB] = __builtin_amdgcn_perm(own, own, wt.sel) ^ 0x80808080u;  // p - 128 as signed bytes
     {
         int l = (int)win[NB], r = (int)win[NB];
 #pragma unroll
@@ -841,7 +859,7 @@ __device__ __forceinline__ void strip_u8(const uint8_t *__restrict__ in, const i
                                          int x0, int y0, int rows, int lane) {
     constexpr int K = 2 * R + 1;
     constexpr int NB = halo_lanes(R);
-    const WeightsU8<R> wt(filt);
+    WeightsU8<R> wt(filt);
     const int xs = x0 + 4 * (lane - NB);
     const bool out_lane = (lane >= NB) && (lane < kLanes - NB) && (xs < w);
     int acc[K][4];
@@ -849,12 +867,16 @@ __device__ __forceinline__ void strip_u8(const uint8_t *__restrict__ in, const i
     for (int s = 0; s < K; ++s)
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[s][k] = 0;
-    if (aligned && x0 + 4 * (kLanes - NB) <= w)
+    if (aligned && x0 + 4 * (kLanes - NB) <= w) {
+        wt.sel = load_sel_u8<kFast>(xs, w);
         rows_u8<R, kFast>(wt, in, out, acc, h, w, shift, xs, y0, rows, out_lane);
-    else if (aligned && w >= 4)
+    } else if (aligned && w >= 4) {
+        wt.sel = load_sel_u8<kEdge>(xs, w);
         rows_u8<R, kEdge>(wt, in, out, acc, h, w, shift, xs, y0, rows, out_lane);
-    else
+    } else {
+        wt.sel = load_sel_u8<kTiny>(xs, w);
         rows_u8<R, kTiny>(wt, in, out, acc, h, w, shift, xs, y0, rows, out_lane);
+    }
 }
 
 // Wave tile (sx, sy) of a plane covers rows [sy h / strips_y, (sy+1) h /
