@@ -187,33 +187,20 @@ __device__ __forceinline__ float pick4(const f4u &t, int i) {
     return i == 0 ? t.x : (i == 1 ? t.y : (i == 2 ? t.z : t.w));
 }
 
-// Load one row for a lane: columns xs .. xs+3 clamped to [0, w-1], and for
-// an aligned strip the halo values (clamped too; in kFast a strip flush
-// with the image edge takes its halo from its own edge column).
+// Load one row for a lane: the loaded values as they come from memory
+// (finish_row turns them into columns xs .. xs+3 clamped to [0, w-1] and,
+// for an aligned strip, the clamped halo values). The selection is left to
+// the fold so that the loads of the next chunk are not waited for when
+// they are issued.
 template <int R, int MODE>
 __device__ __forceinline__ void load_row(const float *__restrict__ row, int xs, int x0, int w, int lane,
                                          RowF32<R> &q) {
-    if constexpr (MODE == kFast) {
-        if constexpr (idle_lanes(R) > 0) {
-            // The left halo lane of the first strip sits left of column 0.
-            const f4u t = ld(reinterpret_cast<const f4u *>(row + vec_load_col(R, kFast, xs, w)));
-            const bool left_of_image = xs < 0;
-            q.v[0] = t.x;
-            q.v[1] = left_of_image ? t.x : t.y;
-            q.v[2] = left_of_image ? t.x : t.z;
-            q.v[3] = left_of_image ? t.x : t.w;
-        } else {
-            const f4u t = ld(reinterpret_cast<const f4u *>(row + vec_load_col(R, kFast, xs, w)));
-            q.v[0] = t.x;
-            q.v[1] = t.y;
-            q.v[2] = t.z;
-            q.v[3] = t.w;
-        }
-    } else if constexpr (MODE == kEdge) {
-        const int xa = vec_load_col(R, kEdge, xs, w);
-        const f4u t = ld(reinterpret_cast<const f4u *>(row + xa));
-#pragma unroll
-        for (int k = 0; k < 4; ++k) q.v[k] = pick4(t, clampi(xs + k, 0, w - 1) - xa);
+    if constexpr (MODE == kFast || MODE == kEdge) {
+        const f4u t = ld(reinterpret_cast<const f4u *>(row + vec_load_col(R, MODE, xs, w)));
+        q.v[0] = t.x;
+        q.v[1] = t.y;
+        q.v[2] = t.z;
+        q.v[3] = t.w;
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k) q.v[k] = row[clampi(xs + k, 0, w - 1)];
@@ -221,17 +208,47 @@ __device__ __forceinline__ void load_row(const float *__restrict__ row, int xs, 
     if constexpr (aligned_strip(R)) {
         const bool left = lane < kLanes / 2;
         if constexpr (MODE == kFast) {
-            const int xh = halo_load_col(R, left, x0, w);
-            loadn<R>(row + xh, q.hv);
-            const bool edge = left ? (x0 == 0) : (x0 + 4 * kLanes == w);
-            const float e = left ? q.v[0] : q.v[3];
-#pragma unroll
-            for (int j = 0; j < R; ++j) q.hv[j] = edge ? e : q.hv[j];
+            loadn<R>(row + halo_load_col(R, left, x0, w), q.hv);
         } else {
             const int xh = left ? x0 - R : x0 + 4 * kLanes;
 #pragma unroll
             for (int j = 0; j < R; ++j) q.hv[j] = row[clampi(xh + j, 0, w - 1)];
         }
+    }
+}
+
+// Where a lane sits in its strip: what finish_row needs to clamp a row.
+struct LaneCtx {
+    int xs, x0, w, lane;
+};
+
+// The loaded row as columns xs .. xs+3 clamped to [0, w-1] and, for an
+// aligned strip, its clamped halo values. kFast: the left halo lane of the
+// first strip (left of column 0) replicates column 0, and an aligned strip
+// flush with the image edge takes its halo from its own edge column. kEdge:
+// the lane loaded the 4 in-bounds columns nearest to its own and picks
+// each clamped column from them.
+template <int R, int MODE>
+__device__ __forceinline__ void finish_row(RowF32<R> &q, const LaneCtx &c) {
+    if constexpr (MODE == kFast) {
+        if constexpr (idle_lanes(R) > 0) {
+            const bool left_of_image = c.xs < 0;
+            q.v[1] = left_of_image ? q.v[0] : q.v[1];
+            q.v[2] = left_of_image ? q.v[0] : q.v[2];
+            q.v[3] = left_of_image ? q.v[0] : q.v[3];
+        }
+    } else if constexpr (MODE == kEdge) {
+        const int xa = vec_load_col(R, kEdge, c.xs, c.w);
+        const f4u t = {q.v[0], q.v[1], q.v[2], q.v[3]};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q.v[k] = pick4(t, clampi(c.xs + k, 0, c.w - 1) - xa);
+    }
+    if constexpr (aligned_strip(R) && MODE == kFast) {
+        const bool left = c.lane < kLanes / 2;
+        const bool edge = left ? (c.x0 == 0) : (c.x0 + 4 * kLanes == c.w);
+        const float e = left ? q.v[0] : q.v[3];
+#pragma unroll
+        for (int j = 0; j < R; ++j) q.hv[j] = edge ? e : q.hv[j];
     }
 }
 
@@ -242,6 +259,7 @@ struct Weights {
     float w2[SEP ? 1 : K * K];
     float fx[SEP ? K : 1];
     float fy[SEP ? K : 1];
+    LaneCtx lc;  // set per strip: where this lane sits (see finish_row)
 
     // fa: the (2R+1)^2 taps (DIRECT) or fx (separable kinds); fb: fy.
     __device__ __forceinline__ Weights(const float *__restrict__ fa, const float *__restrict__ fb) {
@@ -269,9 +287,11 @@ struct Weights {
 //   IPRO >= 0: the row is prologue row IPRO (< 2R): skip outputs j < 0.
 // Output j of the strip collects input rows j .. j+2R (dy = -R .. R) and
 // lives in ring slot j mod K.
-template <int R, int VAR, bool EXACT, int RES, int IPRO>
-__device__ __forceinline__ void fold_row_f32(const Weights<R, VAR> &wt, const RowF32<R> &q,
+template <int R, int VAR, bool EXACT, int RES, int IPRO, int MODE>
+__device__ __forceinline__ void fold_row_f32(const Weights<R, VAR> &wt, const RowF32<R> &q0,
                                              float (&acc)[2 * R + 1][4]) {
+    RowF32<R> q = q0;
+    finish_row<R, MODE>(q, wt.lc);
     constexpr int K = 2 * R + 1;
     constexpr int NB = halo_lanes(R);
     constexpr int C = 4 * NB;
@@ -410,7 +430,7 @@ __device__ __forceinline__ void process_chunk(const Weights<R, VAR> &wt, const R
     static_for<0, CH>([&](auto sc) __attribute__((always_inline)) {
         constexpr int s = decltype(sc)::value;
         constexpr int RES = (2 * R + s) % K;
-        fold_row_f32<R, VAR, EXACT, RES, -1>(wt, v[s], acc);
+        fold_row_f32<R, VAR, EXACT, RES, -1, MODE>(wt, v[s], acc);
         constexpr int done = (RES + 1) % K;
         store_row<MODE, idle_lanes(R)>(out, w, xs, y0 + i0 + s - 2 * R, out_lane, acc[done]);
 #pragma unroll
@@ -434,7 +454,7 @@ __device__ __forceinline__ void rows_group_f32(const Weights<R, VAR> &wt, const 
             RowF32<R> v;
             const int yy = clampi(y0 - R + i0 + s, 0, h - 1);
             load_row<R, MODE>(in + (int64_t)yy * w, xs, x0, w, lane, v);
-            fold_row_f32<R, VAR, EXACT, RES, -1>(wt, v, acc);
+            fold_row_f32<R, VAR, EXACT, RES, -1, MODE>(wt, v, acc);
             const int j = i0 + s - 2 * R;
             constexpr int done = (RES + 1) % K;
             if (j >= 0 && j < rows) store_row<MODE, idle_lanes(R)>(out, w, xs, y0 + j, out_lane, acc[done]);
@@ -470,7 +490,7 @@ __device__ __forceinline__ void rows_pipelined_f32(const Weights<R, VAR> &wt, co
             // Prologue: input rows 0 .. 2R-1 complete no output.
             static_for<0, 2 * R>([&](auto ic) __attribute__((always_inline)) {
                 constexpr int i = decltype(ic)::value;
-                fold_row_f32<R, VAR, EXACT, i % K, i>(wt, pv[i], acc);
+                fold_row_f32<R, VAR, EXACT, i % K, i, MODE>(wt, pv[i], acc);
             });
         }
         for (;;) {
@@ -502,8 +522,9 @@ __device__ __forceinline__ void strip_f32(const float *__restrict__ in, const fl
                                           int x0, int y0, int rows, int lane) {
     constexpr int K = 2 * R + 1;
     constexpr int IL = idle_lanes(R);
-    const Weights<R, VAR> wt(fa, fb);
+    Weights<R, VAR> wt(fa, fb);
     const int xs = lane_col(R, x0, lane);
+    wt.lc = LaneCtx{xs, x0, w, lane};
     const bool out_lane = (lane >= IL) && (lane < kLanes - IL) && (xs < w);
     float acc[K][4];
 #pragma unroll
