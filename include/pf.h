@@ -299,7 +299,8 @@ pf_status pf_tune_save(const char *path);
  * `reps` timed runs over buffers rotated through 1 GiB), for r in 0..r_max
  * and the three size
  * classes: every (rows_per_wave in {8, 16, 32, 64}, for PF_KIND_U8 also
- * 12, 20, 24 and 48) x (waves_per_group in {1, 2, 4, 8}) shape of
+ * 12, 20, 24 and 48, for the FP32 kinds also the heights up to 64 that fill
+ * whole row chunks of the radius) x (waves_per_group in {1, 2, 4, 8}) shape of
  * single-image calls of every kind, and for
  * PF_KIND_SEP (r <= PF_SEP_DIRECT_R_MAX) also the PF_VAR_SEP_DIRECT variant
  * at the best shape; and the
@@ -322,7 +323,8 @@ pf_status pf_tune_batch_blocks(int32_t blocks_per_cu, int32_t *previous);
  * per compute unit (1..4, see pf_tune_batch_blocks) x one row-tile height
  * in {8, 16, 32, 64} for every key the batch uses, keeping the fastest
  * point; then for each (kind, r, size class) key the batch uses, the other
- * tile heights, keeping a change only when the batch gets at least 3%
+ * tile heights of that set and those up to 64 that fill whole row chunks of
+ * the key's radius, keeping a change only when the batch gets at least 3%
  * faster. Single-image entries are not touched. Installs the result and
  * writes it to `path` if not NULL. Overwrites `out`. */
 pf_status pf_batch_autotune(int32_t n,

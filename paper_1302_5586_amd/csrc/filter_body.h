@@ -353,20 +353,9 @@ __device__ __forceinline__ void fold_row_f32(const Weights<R, VAR> &wt, const Ro
     }
 }
 
-// Rows per pipelined chunk: a multiple of K (ring residues stay
-// compile-time constants) near CHUNK rows. Single-image launches run many
-// waves per SIMD and take 8; the persistent batch kernel runs two and
-// hides latency with 12 (both measured on MI355X).
-#ifndef PF_CHUNK
-#define PF_CHUNK 8
-#endif
-#ifndef PF_BATCH_CHUNK
-#define PF_BATCH_CHUNK 12
-#endif
 template <int R, int CHUNK>
 constexpr int chunk_rows() {
-    constexpr int K = 2 * R + 1;
-    return K * (CHUNK / K > 0 ? CHUNK / K : 1);
+    return chunk_rows_of(R, CHUNK);
 }
 
 // Load input rows [i0, i0 + CH) of a strip. Rows past the strip's last

@@ -46,6 +46,22 @@ constexpr int strip_width_u8(int r) { return 4 * (64 - 2 * halo_lanes(r)); }
 //               columns, and every strip of radii above 4).
 constexpr int kStripFast = 0, kStripEdge = 1, kStripTiny = 2;
 
+// Rows per pipelined chunk of the FP32 strip: a multiple of K = 2r+1 (ring
+// residues stay compile-time constants) near `chunk` rows. Single-image
+// launches take 8, the persistent batch kernel 12 (both measured on
+// MI355X). Rows past the last whole chunk of a tile are loaded one by one,
+// each waited for at once, so tile heights that fill whole chunks are
+// cheaper (the tuners try them).
+#ifndef PF_CHUNK
+#define PF_CHUNK 8
+#endif
+#ifndef PF_BATCH_CHUNK
+#define PF_BATCH_CHUNK 12
+#endif
+constexpr int chunk_rows_of(int r, int chunk) {
+    return (2 * r + 1) * (chunk / (2 * r + 1) > 0 ? chunk / (2 * r + 1) : 1);
+}
+
 constexpr int clamp_int(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // First column of lane `lane` in a strip starting at column x0.

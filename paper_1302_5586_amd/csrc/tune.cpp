@@ -26,6 +26,17 @@ namespace pf {
 
 namespace {
 
+// Tile heights (multiples of 4 in 8..64) whose rows fill whole chunks of
+// the FP32 strip's row pipeline for radius r (no one-by-one tail rows).
+std::vector<int> whole_chunk_heights(int r, int chunk) {
+    const int ch = chunk_rows_of(r, chunk);
+    std::vector<int> v;
+    for (int by = ch; by <= 64; by += ch)
+        if (by % 4 == 0 && by >= 8) v.push_back(by);
+    return v;
+}
+
+
 constexpr int kKinds = 3;  // PF_KIND_2D, PF_KIND_SEP, PF_KIND_U8
 constexpr int kSizes = 3;
 constexpr int kContexts = 2;  // PF_TUNE_SINGLE, PF_TUNE_BATCH
@@ -428,6 +439,9 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
                 // few waves spread over the SIMDs: finer tile heights too.
                 std::vector<int> cand(bys, bys + 4);
                 if (kind == PF_KIND_U8) cand.insert(cand.end(), {12, 20, 24, 48});
+                else
+                    for (int by : whole_chunk_heights(r, PF_CHUNK))
+                        if (std::find(cand.begin(), cand.end(), by) == cand.end()) cand.push_back(by);
                 for (int by : cand)
                     for (int wpg : wpgs)
                         if (by != dflt.rows_per_wave || wpg != dflt.waves_per_group) shapes.push_back({by, wpg});
@@ -578,9 +592,11 @@ pf_status pf_batch_autotune(int32_t n, const int32_t *__restrict h, const int32_
     // Then coordinate descent over the batch-context keys the batch uses, one
     // key at a time: a new tile height is kept only when the whole batch gets
     // at least 3% faster. Single-image entries are not touched.
-    const int bys[] = {8, 16, 32, 64};
     for (const auto &k : keys) {
         if (st != PF_OK) break;
+        std::vector<int> bys = {8, 16, 32, 64};
+        for (int by : whole_chunk_heights(k[1], PF_BATCH_CHUNK))
+            if (std::find(bys.begin(), bys.end(), by) == bys.end()) bys.push_back(by);
         for (int by : bys) {
             int keep = 0;
             {
