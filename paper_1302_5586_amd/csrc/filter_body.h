@@ -436,13 +436,29 @@ __device__ __forceinline__ void rows_group_f32(const Weights<R, VAR> &wt, const 
                                                int xs, int x0, int lane, int y0, int rows, int i0, int nin,
                                                bool out_lane) {
     constexpr int K = 2 * R + 1;
+    // Radii up to 4: the group's rows are all loaded first (rows past nin
+    // repeat the last one and are not folded), so their loads overlap
+    // instead of each being waited for before the next is issued.
+    constexpr bool AHEAD = R <= 4;
+    RowF32<R> va[AHEAD ? K : 1];
+    if constexpr (AHEAD) {
+        static_for<0, K>([&](auto sc) __attribute__((always_inline)) {
+            constexpr int s = decltype(sc)::value;
+            const int yy = clampi(y0 - R + min(i0 + s, nin - 1), 0, h - 1);
+            load_row<R, MODE>(in + (int64_t)yy * w, xs, x0, w, lane, va[s]);
+        });
+    }
     static_for<0, K>([&](auto sc) __attribute__((always_inline)) {
         constexpr int s = decltype(sc)::value;
         if (i0 + s < nin) {
             constexpr int RES = (OFF + s) % K;
             RowF32<R> v;
-            const int yy = clampi(y0 - R + i0 + s, 0, h - 1);
-            load_row<R, MODE>(in + (int64_t)yy * w, xs, x0, w, lane, v);
+            if constexpr (AHEAD) {
+                v = va[s];
+            } else {
+                const int yy = clampi(y0 - R + i0 + s, 0, h - 1);
+                load_row<R, MODE>(in + (int64_t)yy * w, xs, x0, w, lane, v);
+            }
             fold_row_f32<R, VAR, EXACT, RES, -1, MODE>(wt, v, acc);
             const int j = i0 + s - 2 * R;
             constexpr int done = (RES + 1) % K;
@@ -805,11 +821,21 @@ __device__ __forceinline__ void rows_group_u8(const WeightsU8<R> &wt, const uint
                                               uint8_t *__restrict__ out, int (&acc)[2 * R + 1][4], int h, int w,
                                               int shift, int xs, int y0, int rows, int i0, int nin, bool out_lane) {
     constexpr int K = 2 * R + 1;
+    // Radii up to 4: all the group's rows are loaded first (as in
+    // rows_group_f32).
+    constexpr bool AHEAD = R <= 4;
+    uint32_t va[AHEAD ? K : 1];
+    if constexpr (AHEAD) {
+#pragma unroll
+        for (int s = 0; s < K; ++s)
+            va[s] = load_u8<MODE>(in + (int64_t)clampi(y0 - R + min(i0 + s, nin - 1), 0, h - 1) * w, xs, w);
+    }
     static_for<0, K>([&](auto sc) __attribute__((always_inline)) {
         constexpr int s = decltype(sc)::value;
         if (i0 + s < nin) {
             constexpr int RES = (OFF + s) % K;
-            const uint32_t v = load_u8<MODE>(in + (int64_t)clampi(y0 - R + i0 + s, 0, h - 1) * w, xs, w);
+            const uint32_t v =
+                AHEAD ? va[AHEAD ? s : 0] : load_u8<MODE>(in + (int64_t)clampi(y0 - R + i0 + s, 0, h - 1) * w, xs, w);
             fold_row_u8<R, RES, -1>(wt, v, acc);
             const int j = i0 + s - 2 * R;
             constexpr int done = (RES + 1) % K;
