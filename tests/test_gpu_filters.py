@@ -219,3 +219,36 @@ def test_u8_group_shapes_bit_exact(r):
                 pf.tune_reset()
             bad = int((got != ref).sum())
             assert bad == 0, "u8 r=%d %dx%dx%d by=%d wpg=%d: %d bytes differ" % (r, c, h, w, by, wpg, bad)
+
+
+def test_class_autotune_keeps_results(tmp_path):
+    """The class tuner changes only launch shapes and variants: after it (and
+    after reloading the table it saved), single-image calls of every kind
+    still match the oracle, FP32 within the bound and uint8 bit for bit, in
+    all three size classes."""
+    dev = device()
+    path = str(tmp_path / "class.json")
+    rng = np.random.default_rng(4242)
+    try:
+        pf.autotune(r_max=2, reps=2, path=path)
+        pf.tune_reset()
+        pf.tune_load(path)
+        for r in (0, 1, 2):
+            for h, w in ((37, 301), (129, 250), (300, 1100), (1100, 1300)):
+                img = rng.random((h, w), dtype=np.float32)
+                f = _rand_filter(rng, r)
+                got = pf.filter2d(_t(img, dev), _t(f, dev)).cpu().numpy()
+                assert_close(got, oracle.filter2d_f32(img, f), tolerance_2d(img, f, r),
+                             "tuned 2d r=%d %dx%d" % (r, h, w))
+                fx = rng.random(2 * r + 1).astype(np.float32)
+                fy = rng.random(2 * r + 1).astype(np.float32)
+                got = pf.filter_sep(_t(img, dev), _t(fx, dev), _t(fy, dev)).cpu().numpy()
+                assert_close(got, oracle.filter_sep_f32(img, fx, fy), tolerance_sep(img, fx, fy),
+                             "tuned sep r=%d %dx%d" % (r, h, w))
+            for c, h, w in ((3, 40, 300), (1, 700, 500), (3, 600, 800)):
+                img = rng.integers(0, 256, (c, h, w), dtype=np.uint8)
+                f8 = rng.integers(-8, 9, (2 * r + 1, 2 * r + 1)).astype(np.int8)
+                got = pf.filter2d_u8(_t(img, dev), _t(f8, dev), 6).cpu().numpy()
+                assert np.array_equal(got, oracle.filter2d_u8(img, f8, 6)), "tuned u8 r=%d %dx%dx%d" % (r, c, h, w)
+    finally:
+        pf.tune_reset()
