@@ -49,9 +49,9 @@ constexpr int kStripFast = 0, kStripEdge = 1, kStripTiny = 2;
 // Rows per pipelined chunk of the FP32 strip: a multiple of K = 2r+1 (ring
 // residues stay compile-time constants) near `chunk` rows. Single-image
 // launches take 8, the persistent batch kernel 12 (both measured on
-// MI355X). Rows past the last whole chunk of a tile are loaded one by one,
-// each waited for at once, so tile heights that fill whole chunks are
-// cheaper (the tuners try them).
+// MI355X). Rows past the last whole chunk of a tile are taken in groups of
+// 2r+1 with a wait per group, so tile heights that fill whole chunks skip
+// that tail (the tuners try them).
 #ifndef PF_CHUNK
 #define PF_CHUNK 8
 #endif
