@@ -46,6 +46,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: dot4 lane-ops/s
+MFMA_INT8_PEAK = 5.0e15        # MI355X dense int8 matrix ops/s, published
 # Server settings for every served run: three streams keep a batch on the
 # device while the next is packed; batches of up to 256 requests keep the
 # per-batch host work small next to the kernel at saturation.
@@ -77,7 +78,8 @@ def parse():
 
 KERNEL_SOURCES = ("paper_1302_5586_amd/csrc/filter_body.h", "paper_1302_5586_amd/csrc/pf_internal.h",
                   "paper_1302_5586_amd/csrc/dev_common.h", "paper_1302_5586_amd/csrc/batch_inst.hip",
-                  "paper_1302_5586_amd/csrc/f32_inst.hip", "paper_1302_5586_amd/csrc/launch.hip")
+                  "paper_1302_5586_amd/csrc/f32_inst.hip", "paper_1302_5586_amd/csrc/launch.hip",
+                  "paper_1302_5586_amd/csrc/u8_mfma.hip")
 
 
 def kernel_source_hash():
@@ -516,36 +518,55 @@ def main():
         fn = lambda i: pf.filter2d_u8(xu, fu, cfg.shift, out=ou)  # noqa: E731
         fn(0)
         ms_host = time_events(torch, fn, 200, stream)
-        # A 10 us kernel launched back to back from Python is timed by the
-        # host's launch rate as much as by the GPU: the rate reported is
-        # that of the same calls captured once in a graph and replayed.
-        side = torch.cuda.Stream()
-        side.wait_stream(stream)
-        with torch.cuda.stream(side):
-            fn(0)
-        stream.wait_stream(side)
-        torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            for _ in range(20):
+
+        def graph_ms():
+            # A 6-10 us kernel launched back to back from Python is timed by
+            # the host's launch rate as much as by the GPU: the rate reported
+            # is that of the same calls captured once in a graph and replayed.
+            side = torch.cuda.Stream()
+            side.wait_stream(stream)
+            with torch.cuda.stream(side):
                 fn(0)
-        g.replay()
-        torch.cuda.synchronize()
-        ms = time_events(torch, lambda i: g.replay(), 10, stream) / 20
-        del g
+            stream.wait_stream(side)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                for _ in range(20):
+                    fn(0)
+            g.replay()
+            torch.cuda.synchronize()
+            t = time_events(torch, lambda i: g.replay(), 10, stream) / 20
+            del g
+            return t
+
         npx = cfg.c * cfg.h * cfg.w
+        e = pf.tune_lookup(pf.KIND_U8, cfg.r, npx)
+        ms = graph_ms()
+        # The v_dot4 kernel at its tuned shape, for comparison.
+        pf.tune_set([pf.TuneEntry(kind=pf.KIND_U8, r=cfg.r, size_class=2, variant=pf.VAR_DIRECT, rows_per_wave=16,
+                                  waves_per_group=1, us=0.0, context=pf.TUNE_SINGLE)])
+        ms_dot4 = graph_ms()
+        pf.tune_set([e])
         dot4 = npx * (2 * cfg.r + 1) * ((2 * cfg.r + 1 + 3) // 4)
+        ops = 2 * npx * (2 * cfg.r + 1) ** 2   # algorithmic int8 multiply-adds x 2
         result["rgb_u8"] = {"value": round(npx / (ms * 1e-3) / 1e9, 3), "unit": "Gpixel/s (pixels x channels)",
+                            "variant": "mfma_i8" if e.variant == pf.VAR_MFMA else "dot4",
+                            "rows_per_wave": e.rows_per_wave, "waves_per_group": e.waves_per_group,
                             "us_per_call": round(ms * 1e3, 2),
                             "us_per_call_from_python": round(ms_host * 1e3, 2),
+                            "us_per_call_dot4": round(ms_dot4 * 1e3, 2),
                             "timing": "20 calls captured in a graph, replayed 10 times",
                             "achieved_GBs": round(2 * npx / (ms * 1e-3) / 1e9, 1),
-                            "dot4_lane_ops_per_s": round(dot4 / (ms * 1e-3) / 1e12, 3),
-                            "frac_alu_dot4": round(dot4 / (ms * 1e-3) / VALU_LANE_OPS, 4),
-                            "frac_of_dot4_probe": (round(dot4 / (ms * 1e-3) / probes["dot4_lane_ops_per_s"], 4)
-                                                   if "dot4_lane_ops_per_s" in probes else None),
+                            "frac_hbm": round(2 * npx / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                            "int8_TOPs_algorithmic": round(ops / (ms * 1e-3) / 1e12, 2),
+                            "frac_mfma_int8_peak": round(ops / (ms * 1e-3) / MFMA_INT8_PEAK, 4),
+                            "dot4_kernel_frac_alu_dot4": round(dot4 / (ms_dot4 * 1e-3) / VALU_LANE_OPS, 4),
+                            "dot4_kernel_frac_of_dot4_probe": (
+                                round(dot4 / (ms_dot4 * 1e-3) / probes["dot4_lane_ops_per_s"], 4)
+                                if "dot4_lane_ops_per_s" in probes else None),
                             "workload": "3x1080x1920 uint8 planar, 7x7 int8 weights in -8..8, shift 6, seed 2"}
-        log("rgb_u8: %.2f us/call (graph replay), %.2f us/call from Python" % (ms * 1e3, ms_host * 1e3))
+        log("rgb_u8: %.2f us/call (graph replay, %s), %.2f us/call from Python; v_dot4 kernel %.2f us" % (
+            ms * 1e3, result["rgb_u8"]["variant"], ms_host * 1e3, ms_dot4 * 1e3))
 
     # ---- serving ------------------------------------------------------------
     if "serve" not in skip and args.serve_seconds > 0:

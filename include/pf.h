@@ -92,6 +92,13 @@ typedef int32_t pf_status;
 /* Largest radius PF_VAR_SEP_DIRECT runs at: above it the (2r+1)^2 computed
  * taps no longer fit in registers (PF_EUNSUPPORTED). */
 #define PF_SEP_DIRECT_R_MAX 5
+/* PF_KIND_U8 on the int8 matrix cores (v_mfma_i32_16x16x64_i8) instead of
+ * v_dot4, radius 1..PF_U8_MFMA_R_MAX; same results bit for bit. Its launch
+ * shape: rows_per_wave a multiple of 16, rows_per_wave * waves_per_group
+ * at most PF_U8_MFMA_TILE_MAX (the rows of a workgroup tile of 64 columns). */
+#define PF_VAR_MFMA        3
+#define PF_U8_MFMA_R_MAX   4
+#define PF_U8_MFMA_TILE_MAX 512
 
 /* Border rules: the value an index outside [0, n) of an axis reads. */
 #define PF_BORDER_CLAMP    0  /* nearest edge element: a a | a b c | c c           */

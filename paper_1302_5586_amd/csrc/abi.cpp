@@ -283,7 +283,8 @@ pf_status pf_filter2d_u8(int32_t c, int32_t h, int32_t w, int32_t r, int32_t shi
     const size_t nf = (size_t)(2 * r + 1) * (2 * r + 1);
     if (overlap(filt, nf, out, bytes)) return fail(PF_EALIAS, "filter and output overlap (restrict)");
     const pf_tune_entry e = tune_lookup(PF_KIND_U8, r, (int64_t)c * h * w);
-    hipError_t he = launch_u8(r, in, filt, out, c, h, w, shift, e.rows_per_wave, e.waves_per_group, (hipStream_t)stream);
+    hipError_t he =
+        launch_u8(r, e.variant, in, filt, out, c, h, w, shift, e.rows_per_wave, e.waves_per_group, (hipStream_t)stream);
     if (he != hipSuccess) return fail_hip(he, "kernel launch");
     return PF_OK;
 }

@@ -23,8 +23,18 @@ hipError_t launch_f32(int r, int var, bool exact, const float *in, const float *
     }
 }
 
-hipError_t launch_u8(int r, const uint8_t *in, const int8_t *filt, uint8_t *out, int c, int h, int w, int shift,
-                     int by, int wpg, hipStream_t s) {
+bool u8_variant_ok(int var, int r, int by, int wpg) {
+    if (var == PF_VAR_DIRECT) return true;
+    return var == PF_VAR_MFMA && r >= 1 && r <= PF_U8_MFMA_R_MAX && by % 16 == 0 && by * wpg <= PF_U8_MFMA_TILE_MAX;
+}
+
+hipError_t launch_u8(int r, int var, const uint8_t *in, const int8_t *filt, uint8_t *out, int c, int h, int w,
+                     int shift, int by, int wpg, hipStream_t s) {
+    if (var == PF_VAR_MFMA) {
+        if (!u8_variant_ok(var, r, by, wpg)) return hipErrorInvalidValue;
+        return launch_u8_mfma(r, in, filt, out, c, h, w, shift, by, wpg, s);
+    }
+    if (var != PF_VAR_DIRECT) return hipErrorInvalidValue;
     switch (r) {
         case 0: return dev::launch_u8_t<0>(in, filt, out, c, h, w, shift, by, wpg, s);
         case 1: return dev::launch_u8_t<1>(in, filt, out, c, h, w, shift, by, wpg, s);

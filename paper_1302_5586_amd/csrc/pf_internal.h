@@ -187,8 +187,13 @@ void clear_error();
 // fa: 2D taps (PF_VAR_DIRECT) or fx; fb: fy (ignored for PF_VAR_DIRECT).
 hipError_t launch_f32(int r, int var, bool exact, const float *in, const float *fa, const float *fb, float *out,
                       int h, int w, int by, int wpg, hipStream_t s);
-hipError_t launch_u8(int r, const uint8_t *in, const int8_t *filt, uint8_t *out, int c, int h,
+// var: PF_VAR_DIRECT (v_dot4) or PF_VAR_MFMA (int8 matrix cores, u8_mfma.hip).
+hipError_t launch_u8(int r, int var, const uint8_t *in, const int8_t *filt, uint8_t *out, int c, int h,
                      int w, int shift, int by, int wpg, hipStream_t s);
+hipError_t launch_u8_mfma(int r, const uint8_t *in, const int8_t *filt, uint8_t *out, int c, int h, int w,
+                          int shift, int rpw, int wpg, hipStream_t s);
+// Whether the uint8 variant runs at radius r with this launch shape.
+bool u8_variant_ok(int var, int r, int by, int wpg);
 // Persistent batch kernel over images with r <= 4 (group 0; group 1 is not
 // built and fails with hipErrorInvalidValue), compiled with the variants of
 // `mask` (see batch_mask).

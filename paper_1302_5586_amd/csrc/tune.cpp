@@ -61,9 +61,13 @@ pf_tune_entry default_entry(int ctx, int kind, int r, int sc) {
     e.context = ctx;
     e.variant = (kind == PF_KIND_SEP) ? PF_VAR_SEPARABLE : PF_VAR_DIRECT;
     // Defaults measured on MI355X: 16-row tiles for small images, for
-    // batches and for the uint8 path, 32-row tiles otherwise.
+    // batches and for the uint8 path, 32-row tiles otherwise. uint8 at radii
+    // the matrix-core kernel runs (1.5x faster than v_dot4 at 1080p RGB,
+    // 7 x 7): that kernel, four waves of 16 rows per workgroup.
+    const bool u8_mfma = kind == PF_KIND_U8 && ctx == PF_TUNE_SINGLE && r >= 1 && r <= PF_U8_MFMA_R_MAX;
+    if (u8_mfma) e.variant = PF_VAR_MFMA;
     e.rows_per_wave = (ctx == PF_TUNE_BATCH || sc == 0 || kind == PF_KIND_U8) ? 16 : 32;
-    e.waves_per_group = ctx == PF_TUNE_BATCH ? kBatchWaves : (kind == PF_KIND_U8 ? 1 : 4);
+    e.waves_per_group = ctx == PF_TUNE_BATCH ? kBatchWaves : (kind == PF_KIND_U8 && !u8_mfma ? 1 : 4);
     e.us = 0.0f;
     return e;
 }
@@ -94,6 +98,8 @@ bool entry_ok(const pf_tune_entry &e) {
     // A separable filter called alone may also run as 2D taps fy[i] * fx[j].
     if (e.kind == PF_KIND_SEP)
         return e.variant == PF_VAR_SEPARABLE || (e.variant == PF_VAR_SEP_DIRECT && e.r <= PF_SEP_DIRECT_R_MAX);
+    // uint8 may run on v_dot4 or on the int8 matrix cores.
+    if (e.kind == PF_KIND_U8) return u8_variant_ok(e.variant, e.r, e.rows_per_wave, e.waves_per_group);
     return e.variant == PF_VAR_DIRECT;
 }
 
@@ -450,8 +456,8 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
                         return time_launch(
                             [&](int i) {
                                 const size_t o = (size_t)i * px * planes;
-                                return launch_u8(r, (const uint8_t *)in + o, (const int8_t *)filt, (uint8_t *)outb + o,
-                                                 3, h, w, 6, by, wpg, s);
+                                return launch_u8(r, v, (const uint8_t *)in + o, (const int8_t *)filt,
+                                                 (uint8_t *)outb + o, 3, h, w, 6, by, wpg, s);
                             },
                             nb1, reps, 5, s, us);
                     }
@@ -463,6 +469,14 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
                         },
                         nb1, reps, 5, s, us);
                 };
+                // A default on another variant (uint8 on the matrix cores) is
+                // timed first, so that it keeps its place unless beaten by 3%.
+                if (dflt.variant != var) {
+                    float us = 0.0f;
+                    st = time_single(dflt.variant, dflt.rows_per_wave, dflt.waves_per_group, &us);
+                    if (st != PF_OK) break;
+                    best.us = us;
+                }
                 for (const auto &shape : shapes) {
                     float us = 0.0f;
                     st = time_single(var, shape.first, shape.second, &us);
@@ -472,6 +486,24 @@ pf_status pf_autotune(int32_t r_max, int32_t reps, const char *path) {
                         best.rows_per_wave = shape.first;
                         best.waves_per_group = shape.second;
                         best.us = us;
+                    }
+                }
+                // uint8 on the matrix cores: its own shapes (16-row wave tiles).
+                if (st == PF_OK && kind == PF_KIND_U8 && u8_variant_ok(PF_VAR_MFMA, r, 16, 1)) {
+                    for (int by : {16, 32, 48, 64}) {
+                        for (int wpg : wpgs) {
+                            if (!u8_variant_ok(PF_VAR_MFMA, r, by, wpg)) continue;
+                            float us = 0.0f;
+                            st = time_single(PF_VAR_MFMA, by, wpg, &us);
+                            if (st != PF_OK) break;
+                            if (better(us, best)) {
+                                best.variant = PF_VAR_MFMA;
+                                best.rows_per_wave = by;
+                                best.waves_per_group = wpg;
+                                best.us = us;
+                            }
+                        }
+                        if (st != PF_OK) break;
                     }
                 }
                 // The variant axis: a separable filter may run as 2D taps.

@@ -132,16 +132,28 @@ def test_u8_all_radii(r):
             assert np.array_equal(got, ref), "u8 r=%d c=%d %dx%d shift=%d" % (r, c, h, w, shift)
 
 
-def test_u8_extreme_weights():
+def _u8_entries(r, var, by, wpg):
+    return [pf.TuneEntry(kind=pf.KIND_U8, r=r, size_class=sc, variant=var, rows_per_wave=by, waves_per_group=wpg,
+                         us=0.0, context=pf.TUNE_SINGLE) for sc in range(3)]
+
+
+@pytest.mark.parametrize("var", [pf.VAR_DIRECT, pf.VAR_MFMA])
+def test_u8_extreme_weights(var):
+    """All-(-128) and all-127 9x9 weights (the largest sums of either sign)
+    on v_dot4 and on the matrix cores."""
     dev = device()
     rng = np.random.default_rng(77)
-    for wv in (-128, 127):
-        img = rng.integers(0, 256, (1, 40, 300), dtype=np.uint8)
-        f = np.full((9, 9), wv, np.int8)
-        for shift in (0, 13, 31):
-            ref = oracle.filter2d_u8(img, f, shift)
-            got = pf.filter2d_u8(_t(img, dev), _t(f, dev), shift).cpu().numpy()
-            assert np.array_equal(got, ref)
+    try:
+        pf.tune_set(_u8_entries(4, var, 16, 4 if var == pf.VAR_MFMA else 1))
+        for wv in (-128, 127):
+            img = rng.integers(0, 256, (1, 40, 300), dtype=np.uint8)
+            f = np.full((9, 9), wv, np.int8)
+            for shift in (0, 13, 31):
+                ref = oracle.filter2d_u8(img, f, shift)
+                got = pf.filter2d_u8(_t(img, dev), _t(f, dev), shift).cpu().numpy()
+                assert np.array_equal(got, ref)
+    finally:
+        pf.tune_reset()
 
 
 def test_config_rgb_full():
@@ -219,6 +231,47 @@ def test_u8_group_shapes_bit_exact(r):
                 pf.tune_reset()
             bad = int((got != ref).sum())
             assert bad == 0, "u8 r=%d %dx%dx%d by=%d wpg=%d: %d bytes differ" % (r, c, h, w, by, wpg, bad)
+
+
+# The matrix-core uint8 kernel: one- to eight-wave workgroups, one to eight
+# 16-row wave tiles per wave, up to the 512-row workgroup tile; images
+# smaller than a tile, ragged in both directions, with rows that are not
+# 4-byte aligned (w not a multiple of 4) and with 4-byte aligned rows whose
+# width is not a multiple of the 16-byte stores.
+MFMA_SHAPES = [(16, 1), (16, 4), (32, 2), (48, 4), (64, 8), (128, 4)]
+MFMA_IMAGES = [(1, 1, 1), (3, 1, 9), (2, 9, 1), (1, 3, 4), (2, 17, 4), (3, 37, 301), (2, 70, 250), (1, 65, 68),
+               (1, 300, 5), (3, 1080, 1920)]
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_u8_mfma_shapes_bit_exact(r):
+    dev = device()
+    import torch
+    rng = np.random.default_rng(4300 + r)
+    try:
+        for (c, h, w) in MFMA_IMAGES:
+            img = rng.integers(0, 256, (c, h, w), dtype=np.uint8)
+            f = rng.integers(-128, 128, (2 * r + 1, 2 * r + 1)).astype(np.int8)
+            shift = int(rng.integers(0, 14))
+            ref = oracle.filter2d_u8(img, f, shift)
+            x, fd = _t(img, dev), _t(f, dev)
+            for by, wpg in MFMA_SHAPES:
+                pf.tune_set(_u8_entries(r, pf.VAR_MFMA, by, wpg))
+                got = pf.filter2d_u8(x, fd, shift).cpu().numpy()
+                bad = int((got != ref).sum())
+                assert bad == 0, "mfma u8 r=%d %dx%dx%d shift=%d by=%d wpg=%d: %d bytes differ" % (
+                    r, c, h, w, shift, by, wpg, bad)
+            # input and output one and three bytes past 4-byte alignment
+            buf = torch.empty(img.size + 1, dtype=torch.uint8, device=dev)
+            xu = buf[1:].view(img.shape)
+            xu.copy_(x)
+            obuf = torch.empty(img.size + 3, dtype=torch.uint8, device=dev)
+            ou = obuf[3:].view(img.shape)
+            pf.tune_set(_u8_entries(r, pf.VAR_MFMA, 16, 4))
+            got = pf.filter2d_u8(xu, fd, shift, out=ou).cpu().numpy()
+            assert np.array_equal(got, ref), "mfma u8 unaligned r=%d %dx%dx%d" % (r, c, h, w)
+    finally:
+        pf.tune_reset()
 
 
 def test_class_autotune_keeps_results(tmp_path):
