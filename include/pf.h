@@ -245,11 +245,13 @@ pf_status pf_filter_sep_f32(int32_t h, int32_t w, int32_t r,
  * offset p*h*w), one int8 filter for all planes: acc = sum of int8 weight * uint8 pixel in int32 (exact),
  * q = acc >> shift (arithmetic, i.e. floor), out = min(max(q, 0), 255).
  * c, h, w >= 1; 0 <= r <= PF_R_MAX; 0 <= shift <= 31. in and out disjoint.
- * filt: int8[(2r+1)^2] device. flags must be 0. The tune table's tile
- * height is the tallest tile: the launch keeps the number of rounds of
- * waves per SIMD that height needs and spreads each strip column's rows
- * evenly over as many tiles as fill those rounds (integer sums, so the
- * result does not depend on the split). */
+ * filt: int8[(2r+1)^2] device. flags must be 0. The tune table's variant
+ * picks the kernel: PF_VAR_MFMA (the int8 matrix cores; radii 1..4, the
+ * default there) or PF_VAR_DIRECT (v_dot4, every radius); both give the
+ * same bytes. For v_dot4 the table's tile height is the tallest tile: the
+ * launch keeps the number of rounds of waves per SIMD that height needs
+ * and spreads each strip column's rows evenly over as many tiles as fill
+ * those rounds (integer sums, so the result does not depend on the split). */
 pf_status pf_filter2d_u8(int32_t c, int32_t h, int32_t w, int32_t r, int32_t shift,
                          PF_ARR(const uint8_t, in, c * h * w),
                          PF_ARR(const int8_t, filt, (2 * r + 1) * (2 * r + 1)),
