@@ -95,10 +95,10 @@ typedef int32_t pf_status;
 /* PF_KIND_U8 on the int8 matrix cores (v_mfma_i32_16x16x64_i8) instead of
  * v_dot4, radius 1..PF_U8_MFMA_R_MAX; same results bit for bit. Its launch
  * shape: rows_per_wave a multiple of 16, rows_per_wave * waves_per_group
- * at most PF_U8_MFMA_TILE_MAX (the rows of a workgroup tile of 64 columns). */
+ * at most PF_U8_MFMA_TILE_MAX (the rows of a workgroup tile of 128 columns). */
 #define PF_VAR_MFMA        3
 #define PF_U8_MFMA_R_MAX   4
-#define PF_U8_MFMA_TILE_MAX 512
+#define PF_U8_MFMA_TILE_MAX 256
 
 /* Border rules: the value an index outside [0, n) of an axis reads. */
 #define PF_BORDER_CLAMP    0  /* nearest edge element: a a | a b c | c c           */

@@ -25,12 +25,12 @@
 // adjacent output columns), which it packs into one dword; the wave's
 // dwords go through LDS so that each lane stores 16 contiguous bytes.
 //
-// A workgroup owns a tile of 64 output columns and waves x rows-per-wave
+// A workgroup owns a tile of 128 output columns and waves x rows-per-wave
 // output rows. It stages the tile's input rows (clamped at the image edges,
 // biased by -128 to fit the signed operand) and the zero-padded filter rows
 // in LDS; each lane assembles its band entries from the latter once, and
-// each wave reads its B operands with 16-byte LDS loads, four column blocks
-// at a time. The bias is added back exactly as 128 * sum(weights),
+// each wave reads its B operands with 16-byte LDS loads, eight column
+// blocks at a time. The bias is added back exactly as 128 * sum(weights),
 // the initial value of every accumulator.
 #include "filter_body.h"
 
@@ -40,11 +40,17 @@ namespace dev {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaN = 16;                    // output rows and columns of one MFMA block
-constexpr int kMfmaBlocks = 4;                // column blocks per workgroup tile
-constexpr int kMfmaTileW = kMfmaN * kMfmaBlocks;  // 64 output columns
-constexpr int kMfmaRow = kMfmaTileW + 16;     // LDS bytes per staged row: columns x0 - 4 .. x0 + 75
-constexpr int kMfmaFill = (kMfmaTileW + 8) / 4;  // dwords staged per row: columns x0 - 4 .. x0 + 67
-constexpr int kMfmaStage = 8;                 // staged dwords a thread has in flight at once
+// Column blocks per workgroup tile: 8, so that every output row piece a
+// tile stores is a whole 128-byte line (tiles of 4 blocks wrote 64-byte
+// halves, 1.33x the output bytes, and took 6.6 us against 6.1 us at 1080p
+// RGB, 7 x 7).
+constexpr int kMfmaBlocks = 8;
+constexpr int kMfmaTileW = kMfmaN * kMfmaBlocks;  // output columns of a workgroup tile
+constexpr int kMfmaRow = kMfmaTileW + 16;     // LDS bytes per staged row: columns x0 - 4 .. x0 + W + 11
+constexpr int kMfmaGran = kMfmaBlocks == 8 ? 8 : 4;  // bytes a lane stages per row
+constexpr int kMfmaFill = (kMfmaTileW + 8) / kMfmaGran;  // lanes per staged row: columns x0 - 4 .. x0 + W + 3
+constexpr int kMfmaStage = 8;                 // staged loads a thread has in flight at once
+static_assert((kMfmaTileW + 8) % kMfmaGran == 0, "whole granules per staged row");
 
 constexpr int kTapRow = 64;                   // LDS bytes per zero-padded filter row
 constexpr int kTapOff = 32;                   // byte of tap 0 in a padded row
@@ -88,56 +94,83 @@ __device__ __forceinline__ void stage_taps(const int8_t *__restrict__ filt, uint
     }
 }
 
-// Staged row ly = image row clamp(y0 - r + ly), bytes 4q .. 4q + 3 = columns
-// x0 - 4 + 4q .. (each clamped to the image), minus 128. Rows 0 ..
-// nrows - 1 and dwords 0 .. kMfmaFill - 1: every byte a nonzero tap reads.
-// Lanes 0 .. 53 of a wave stage three rows per pass, lane 18 k + q dword q of
-// one of them, so the column part of every load (clamp, byte selector) is
-// the lane's own constant. ALIGNED (rows 4-byte aligned, so w is a multiple
-// of 4 and a dword is either inside the image or wholly left or right of
-// it): one dword load from the clamped position and, at the edges, a byte
-// broadcast; else four byte loads of clamped columns. Loads are
+// Staged row ly = image row clamp(y0 - r + ly), bytes G q .. G q + G - 1 =
+// columns x0 - 4 + G q .. (each clamped to the image), minus 128, for G =
+// kMfmaGran. Rows 0 .. nrows - 1 and granules 0 .. kMfmaFill - 1: every byte
+// a nonzero tap reads. The lanes of a wave stage 64 / kMfmaFill rows per
+// pass, lane kMfmaFill k + q granule q of one of them, so the column part of
+// every load (clamp, byte selectors) is the lane's own constant. ALIGNED
+// (rows 4-byte aligned and w >= G, so w is a multiple of 4 and each dword
+// of a granule is either inside the image or wholly left or right of it):
+// one G-byte load from the clamped position, each dword of it picked by a
+// byte selector (identity inside; a broadcast of the edge byte outside);
+// else one byte load per byte, of the clamped column. Loads are
 // unconditional (clamped rows) and issued kMfmaStage at a time; `between`
 // runs after the first batch is issued, before any of it is written.
 template <int R, bool ALIGNED, class F>
 __device__ __forceinline__ void stage_rows(const uint8_t *__restrict__ plane, uint8_t *rows, int h, int w, int x0,
                                            int y0, int nrows, int wave, int nwaves, int lane, F &&between) {
+    constexpr int G = kMfmaGran, ND = G / 4;
     constexpr int PER = kLanes / kMfmaFill;  // rows per wave per pass
+    typedef uint32_t gran_t __attribute__((ext_vector_type(ND)));
     const int lr = lane / kMfmaFill, q = lane - lr * kMfmaFill;
     const bool active = lr < PER;
-    const int xc = x0 - 4 + 4 * q;
-    uint32_t xo[ALIGNED ? 1 : 4];
-    uint32_t sel = 0x03020100u;
+    const int xc = x0 - 4 + G * q;
+    uint32_t xa = 0, sel[ND];
+    uint32_t xo[ALIGNED ? 1 : G];
     if constexpr (ALIGNED) {
-        xo[0] = (uint32_t)clampi(xc, 0, w - 4);
-        sel = xc < 0 ? 0x00000000u : (xc + 4 > w ? 0x03030303u : 0x03020100u);
+        xa = (uint32_t)clampi(xc, 0, w - G);
+#pragma unroll
+        for (int j = 0; j < ND; ++j) {
+            sel[j] = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sel[j] |= (uint32_t)(clampi(xc + 4 * j + k, 0, w - 1) - (int)xa) << (8 * k);
+        }
+        xo[0] = xa;
     } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) xo[j] = (uint32_t)clampi(xc + j, 0, w - 1);
+        for (int j = 0; j < G; ++j) xo[j] = (uint32_t)clampi(xc + j, 0, w - 1);
     }
-    uint8_t *dst = rows + lr * kMfmaRow + 4 * q;
+    uint8_t *dst = rows + lr * kMfmaRow + G * q;
     const int step = PER * nwaves;
     for (int base = PER * wave; base < nrows; base += kMfmaStage * step) {
-        uint32_t v[kMfmaStage];
+        gran_t v[kMfmaStage];
 #pragma unroll
         for (int u = 0; u < kMfmaStage; ++u) {
             const int ly = min(base + u * step + lr, nrows - 1);
             const uint32_t roff = (uint32_t)clampi(y0 - R + ly, 0, h - 1) * (uint32_t)w;
             if constexpr (ALIGNED) {
-                const uint32_t d = *(const uint32_t *)(plane + (roff + xo[0]));
-                v[u] = __builtin_amdgcn_perm(d, d, sel);
-            } else {
-                uint32_t d = 0u;
+                if constexpr (ND == 1) {
+                    const uint32_t d = *(const uint32_t *)(plane + (roff + xo[0]));
+                    v[u][0] = __builtin_amdgcn_perm(d, d, sel[0]);
+                } else {
+                    // 8 bytes: selector values 0..3 pick bytes of the first
+                    // dword, 4..7 bytes of the second.
+                    typedef uint32_t u2 __attribute__((ext_vector_type(2), aligned(4)));
+                    const u2 d = *(const u2 *)(plane + (roff + xo[0]));
 #pragma unroll
-                for (int j = 0; j < 4; ++j) d |= (uint32_t)plane[roff + xo[j]] << (8 * j);
-                v[u] = d;
+                    for (int j = 0; j < ND; ++j) v[u][j] = __builtin_amdgcn_perm(d[1], d[0], sel[j]);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < ND; ++j) {
+                    uint32_t d = 0u;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) d |= (uint32_t)plane[roff + xo[4 * j + k]] << (8 * k);
+                    v[u][j] = d;
+                }
             }
         }
         if (base == PER * wave) between();
 #pragma unroll
         for (int u = 0; u < kMfmaStage; ++u) {
             const int r0 = base + u * step;
-            if (active && r0 + lr < nrows) *(uint32_t *)(dst + r0 * kMfmaRow) = v[u] ^ 0x80808080u;
+            if (active && r0 + lr < nrows) {
+                gran_t o;
+#pragma unroll
+                for (int j = 0; j < ND; ++j) o[j] = v[u][j] ^ 0x80808080u;
+                *(gran_t *)(dst + r0 * kMfmaRow) = o;
+            }
         }
     }
 }
@@ -209,7 +242,7 @@ __global__ __launch_bounds__(512) void k_filter_u8_mfma(const uint8_t *__restric
     const int nwaves = nthr / kLanes;
     // The taps' loads are issued while the first rows' loads are in flight.
     auto taps_step = [&]() __attribute__((always_inline)) { stage_taps<R>(filt, taps, tid, nthr); };
-    if (aligned)
+    if (aligned && w >= kMfmaGran)
         stage_rows<R, true>(in + plane, rows, h, w, x0, y0, nstage, wave, nwaves, lane, taps_step);
     else
         stage_rows<R, false>(in + plane, rows, h, w, x0, y0, nstage, wave, nwaves, lane, taps_step);
@@ -259,15 +292,21 @@ __global__ __launch_bounds__(512) void k_filter_u8_mfma(const uint8_t *__restric
             }
         }
         // Lane (m, g) puts row m, columns 16 b + 4 g .. + 3 into the wave's LDS
-        // rows; lane 4 r + c then stores row r, columns 16 c .. + 15. Stored
-        // straight from the MFMA layout (16 rows of 16 bytes per store
-        // instruction, each 64-byte row piece written by four of them) the
+        // rows; then each row's bytes leave as 16-byte stores of consecutive
+        // lanes (LPR lanes per row, 64 / LPR rows per store instruction).
+        // Stored straight from the MFMA layout (16 rows of 16 bytes per store
+        // instruction, each row piece written by several of them) the 64-column
         // kernel took 11.5 us instead of 6.4 us at 1080p RGB, 7 x 7.
 #pragma unroll
         for (int b = 0; b < kMfmaBlocks; ++b)
             *(uint32_t *)(obuf + m * kMfmaRow + kMfmaN * b + 4 * g) = pack_mfma_u8(acc[b], shift);
-        const v4i v = *(const v4i *)(obuf + (lane >> 2) * kMfmaRow + 16 * (lane & 3));
-        store16_mfma_u8(rs, h, w, y0 + r0 + (lane >> 2), x0 + 16 * (lane & 3), aligned != 0, v);
+        constexpr int LPR = kMfmaTileW / 16, RPI = kLanes / LPR;
+#pragma unroll
+        for (int i = 0; i < kMfmaN / RPI; ++i) {
+            const int rr = RPI * i + lane / LPR, cc = 16 * (lane % LPR);
+            const v4i v = *(const v4i *)(obuf + rr * kMfmaRow + cc);
+            store16_mfma_u8(rs, h, w, y0 + r0 + rr, x0 + cc, aligned != 0, v);
+        }
     }
 }
 
@@ -277,7 +316,7 @@ hipError_t launch_u8_mfma_t(const uint8_t *in, const int8_t *filt, uint8_t *out,
     rpw = std::max(kMfmaN, (rpw + kMfmaN - 1) / kMfmaN * kMfmaN);
     const int tile_rows = rpw * wpg;
     const int lds = mfma_lds_bytes<R>(tile_rows, wpg);
-    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    if (lds > 64 * 1024) return hipErrorInvalidValue;  // PF_U8_MFMA_TILE_MAX rows fit
     const int64_t tiles_x = cdiv(w, kMfmaTileW), tiles_y = cdiv(h, tile_rows);
     const int64_t per_plane = tiles_x * tiles_y;
     const int64_t ntiles = per_plane * c;

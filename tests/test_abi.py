@@ -155,7 +155,7 @@ def test_tune_table_roundtrip(lib, tmp_path):
 def test_u8_variant_entries(lib):
     """uint8 runs on v_dot4 at every radius, on the matrix cores at radii
     1..4 (the default there) with wave tiles of 16k rows and workgroup tiles
-    of at most 512 rows; other variants and shapes are refused."""
+    of at most 256 rows; other variants and shapes are refused."""
     pf.tune_reset()
     for r in range(pf.PF_R_MAX + 1):
         e = pf.tune_lookup(pf.KIND_U8, r, 1080 * 1920 * 3)
@@ -168,10 +168,11 @@ def test_u8_variant_entries(lib):
         return pf.TuneEntry(kind=pf.KIND_U8, r=r, size_class=2, variant=var, rows_per_wave=by, waves_per_group=wpg,
                             context=pf.TUNE_SINGLE)
     try:
-        pf.tune_set([u8(3, pf.VAR_MFMA, 64, 8), u8(1, pf.VAR_MFMA, 128, 4), u8(4, pf.VAR_DIRECT, 12, 8)])
-        assert pf.tune_lookup(pf.KIND_U8, 3, 1 << 22).rows_per_wave == 64
+        pf.tune_set([u8(3, pf.VAR_MFMA, 32, 8), u8(1, pf.VAR_MFMA, 128, 2), u8(4, pf.VAR_DIRECT, 12, 8)])
+        assert pf.tune_lookup(pf.KIND_U8, 3, 1 << 22).rows_per_wave == 32
         for bad in (u8(0, pf.VAR_MFMA, 16, 4), u8(5, pf.VAR_MFMA, 16, 4), u8(3, pf.VAR_MFMA, 24, 1),
-                    u8(3, pf.VAR_MFMA, 128, 8), u8(3, pf.VAR_SEPARABLE, 16, 1), u8(3, pf.VAR_SEP_DIRECT, 16, 1)):
+                    u8(3, pf.VAR_MFMA, 64, 8), u8(3, pf.VAR_MFMA, 128, 4), u8(3, pf.VAR_SEPARABLE, 16, 1),
+                    u8(3, pf.VAR_SEP_DIRECT, 16, 1)):
             with pytest.raises(pf.PFInvalid):
                 pf.tune_set([bad])
         with pytest.raises(pf.PFInvalid):   # the 2D FP32 kind has no matrix-core variant

@@ -234,11 +234,11 @@ def test_u8_group_shapes_bit_exact(r):
 
 
 # The matrix-core uint8 kernel: one- to eight-wave workgroups, one to eight
-# 16-row wave tiles per wave, up to the 512-row workgroup tile; images
+# 16-row wave tiles per wave, up to the 256-row workgroup tile; images
 # smaller than a tile, ragged in both directions, with rows that are not
 # 4-byte aligned (w not a multiple of 4) and with 4-byte aligned rows whose
 # width is not a multiple of the 16-byte stores.
-MFMA_SHAPES = [(16, 1), (16, 4), (32, 2), (48, 4), (64, 8), (128, 4)]
+MFMA_SHAPES = [(16, 1), (16, 4), (32, 2), (48, 4), (32, 8), (128, 2)]
 MFMA_IMAGES = [(1, 1, 1), (3, 1, 9), (2, 9, 1), (1, 3, 4), (2, 17, 4), (3, 37, 301), (2, 70, 250), (1, 65, 68),
                (1, 300, 5), (3, 1080, 1920)]
 
