@@ -142,7 +142,7 @@ def main():
     stream = torch.cuda.current_stream()
     if args.autotune:
         t0 = time.time()
-        pf.autotune(r_max=4, reps=20)
+        pf.autotune(r_max=pf.PF_R_MAX, reps=20)
         log("class autotune done (%.1f s)" % (time.time() - t0))
     elif os.path.exists(args.tune):
         pf.tune_load(args.tune)

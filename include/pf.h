@@ -97,7 +97,7 @@ typedef int32_t pf_status;
  * shape: rows_per_wave a multiple of 16, rows_per_wave * waves_per_group
  * at most PF_U8_MFMA_TILE_MAX (the rows of a workgroup tile of 128 columns). */
 #define PF_VAR_MFMA        3
-#define PF_U8_MFMA_R_MAX   4
+#define PF_U8_MFMA_R_MAX   8
 #define PF_U8_MFMA_TILE_MAX 256
 
 /* Border rules: the value an index outside [0, n) of an axis reads. */
@@ -246,7 +246,7 @@ pf_status pf_filter_sep_f32(int32_t h, int32_t w, int32_t r,
  * q = acc >> shift (arithmetic, i.e. floor), out = min(max(q, 0), 255).
  * c, h, w >= 1; 0 <= r <= PF_R_MAX; 0 <= shift <= 31. in and out disjoint.
  * filt: int8[(2r+1)^2] device. flags must be 0. The tune table's variant
- * picks the kernel: PF_VAR_MFMA (the int8 matrix cores; radii 1..4, the
+ * picks the kernel: PF_VAR_MFMA (the int8 matrix cores; radii 1..8, the
  * default there) or PF_VAR_DIRECT (v_dot4, every radius); both give the
  * same bytes. For v_dot4 the table's tile height is the tallest tile: the
  * launch keeps the number of rounds of waves per SIMD that height needs

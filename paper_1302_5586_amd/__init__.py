@@ -35,7 +35,7 @@ KIND_2D, KIND_SEP, KIND_U8 = 0, 1, 2
 VAR_DIRECT, VAR_SEPARABLE, VAR_SEP_DIRECT = 0, 1, 2
 # uint8 on the int8 matrix cores (radius 1..PF_U8_MFMA_R_MAX, wave tiles of 16k rows).
 VAR_MFMA = 3
-PF_U8_MFMA_R_MAX = 4
+PF_U8_MFMA_R_MAX = 8
 PF_U8_MFMA_TILE_MAX = 256
 BORDER_CLAMP, BORDER_ZERO, BORDER_REFLECT, BORDER_MIRROR = 0, 1, 2, 3
 OP_SUM_F32, OP_HIST_U8 = 1, 2

@@ -1,4 +1,4 @@
-// The uint8 filter on the int8 matrix cores (radius 1..PF_U8_MFMA_R_MAX).
+// The uint8 filter on the int8 matrix cores (radius 1..PF_U8_MFMA_R_MAX = 8).
 //
 // At a 7 x 7 filter the uint8 path does 49 multiply-adds per byte read, far
 // more than v_dot4 can issue per byte of HBM bandwidth, so the v_dot4
@@ -8,9 +8,11 @@
 //   out[y][x0 + i] = sum over tap row dy and byte column c of
 //                    T[i][(dy, c)] * P[(dy, c)][y],
 //
-// P[(dy, c)][y] = pixel (row y + dy - r, column x0 - 4 + c) of the image,
+// P[(dy, c)][y] = pixel (row y + dy - r, column x0 - 8 + c) of the image,
 // c = 0..31, and T the filter laid out as a Toeplitz band:
-// T[i][(dy, c)] = f[dy][c - i - 4 + r] where that tap exists, else 0. One
+// T[i][(dy, c)] = f[dy][c - i - 8 + r] where that tap exists, else 0 (the
+// taps of output column i sit at c = i + 8 - r .. i + 8 + r, inside 0..31
+// for every r <= 8). One
 // MFMA k-step of 64 bytes covers two tap rows, so a 2r+1 filter takes r+1
 // steps (the last one with a zero tap row when 2r+1 is odd). Each output
 // is its definition's sum of integer products, computed exactly in int32,
@@ -46,11 +48,12 @@ constexpr int kMfmaN = 16;                    // output rows and columns of one 
 // RGB, 7 x 7).
 constexpr int kMfmaBlocks = 8;
 constexpr int kMfmaTileW = kMfmaN * kMfmaBlocks;  // output columns of a workgroup tile
-constexpr int kMfmaRow = kMfmaTileW + 16;     // LDS bytes per staged row: columns x0 - 4 .. x0 + W + 11
+constexpr int kMfmaLeft = 8;                  // staged columns left of the tile
+constexpr int kMfmaRow = kMfmaTileW + 16;     // LDS bytes per staged row: columns x0 - 8 .. x0 + W + 7
 constexpr int kMfmaGran = kMfmaBlocks == 8 ? 8 : 4;  // bytes a lane stages per row
-constexpr int kMfmaFill = (kMfmaTileW + 8) / kMfmaGran;  // lanes per staged row: columns x0 - 4 .. x0 + W + 3
+constexpr int kMfmaFill = kMfmaRow / kMfmaGran;  // lanes per staged row: every byte of it
 constexpr int kMfmaStage = 8;                 // staged loads a thread has in flight at once
-static_assert((kMfmaTileW + 8) % kMfmaGran == 0, "whole granules per staged row");
+static_assert(kMfmaRow % kMfmaGran == 0, "whole granules per staged row");
 
 constexpr int kTapRow = 64;                   // LDS bytes per zero-padded filter row
 constexpr int kTapOff = 32;                   // byte of tap 0 in a padded row
@@ -71,31 +74,33 @@ constexpr int mfma_lds_bytes(int tile_rows, int waves) {
 // The filter rows, zero-padded, in LDS: padded row dy (0 .. 2 steps - 1)
 // is kTapRow bytes, byte kTapOff + t = tap t (0 <= t <= 2r) of filter row
 // dy, every other byte (and every row dy > 2r) 0. Only dwords kTapOff/4 ..
-// +2 of a row hold taps; their threads load the row's taps at fixed offsets
+// +4 of a row hold taps; their threads load the row's taps at fixed offsets
 // from one address (all in flight together). Lane 16 g + i then reads the
-// 16 bytes of its Toeplitz band entry, taps c - i - 4 + r for c = 16 (g % 2)
+// 16 bytes of its Toeplitz band entry, taps c - i - 8 + r for c = 16 (g % 2)
 // .. +15, as a byte-shifted window of padded row 2s + g/2.
 template <int R>
 __device__ __forceinline__ void stage_taps(const int8_t *__restrict__ filt, uint32_t *taps, int tid, int nthr) {
     constexpr int K = 2 * R + 1;
     constexpr int DW = kTapRow / 4;
-    static_assert(K <= 12, "three dwords of taps per filter row");
+    constexpr int TW = (K + 3) / 4;  // dwords of taps per filter row
+    static_assert(TW <= 5, "taps of a row within dwords kTapOff/4 .. +4");
     for (int d = tid; d < 2 * mfma_steps<R>() * DW; d += nthr) {
         const int dy = d / DW, c = d % DW - kTapOff / 4;
         uint32_t v = 0u;
-        if (dy < K && c >= 0 && c < 3) {
+        if (dy < K && c >= 0 && c < TW) {
             const int8_t *frow = filt + dy * K;
-            uint32_t tw[3] = {0u, 0u, 0u};
+            uint32_t tw[TW] = {};
 #pragma unroll
             for (int t = 0; t < K; ++t) tw[t >> 2] |= (uint32_t)(uint8_t)frow[t] << (8 * (t & 3));
-            v = c == 0 ? tw[0] : (c == 1 ? tw[1] : tw[2]);
+#pragma unroll
+            for (int k = 0; k < TW; ++k) v = c == k ? tw[k] : v;
         }
         taps[d] = v;
     }
 }
 
 // Staged row ly = image row clamp(y0 - r + ly), bytes G q .. G q + G - 1 =
-// columns x0 - 4 + G q .. (each clamped to the image), minus 128, for G =
+// columns x0 - 8 + G q .. (each clamped to the image), minus 128, for G =
 // kMfmaGran. Rows 0 .. nrows - 1 and granules 0 .. kMfmaFill - 1: every byte
 // a nonzero tap reads. The lanes of a wave stage 64 / kMfmaFill rows per
 // pass, lane kMfmaFill k + q granule q of one of them, so the column part of
@@ -115,7 +120,7 @@ __device__ __forceinline__ void stage_rows(const uint8_t *__restrict__ plane, ui
     typedef uint32_t gran_t __attribute__((ext_vector_type(ND)));
     const int lr = lane / kMfmaFill, q = lane - lr * kMfmaFill;
     const bool active = lr < PER;
-    const int xc = x0 - 4 + G * q;
+    const int xc = x0 - kMfmaLeft + G * q;
     uint32_t xa = 0, sel[ND];
     uint32_t xo[ALIGNED ? 1 : G];
     if constexpr (ALIGNED) {
@@ -250,8 +255,8 @@ __global__ __launch_bounds__(512) void k_filter_u8_mfma(const uint8_t *__restric
 
     const int m = lane & 15, g = lane >> 4;
     // A operand of step s: 16 bytes of padded row 2s + g/2 from byte pa
-    // (14 <= pa <= 48), read as five dwords and shifted by pa mod 4 bytes.
-    const int pa = kTapOff + 16 * (g & 1) - m - 4 + R;
+    // (10 <= pa <= 48), read as five dwords and shifted by pa mod 4 bytes.
+    const int pa = kTapOff + 16 * (g & 1) - m - kMfmaLeft + R;
     const int pq = pa >> 2, pb = pa & 3;
     v4i a[NS];
 #pragma unroll
@@ -336,6 +341,10 @@ hipError_t launch_u8_mfma(int r, const uint8_t *in, const int8_t *filt, uint8_t 
         case 2: return dev::launch_u8_mfma_t<2>(in, filt, out, c, h, w, shift, rpw, wpg, s);
         case 3: return dev::launch_u8_mfma_t<3>(in, filt, out, c, h, w, shift, rpw, wpg, s);
         case 4: return dev::launch_u8_mfma_t<4>(in, filt, out, c, h, w, shift, rpw, wpg, s);
+        case 5: return dev::launch_u8_mfma_t<5>(in, filt, out, c, h, w, shift, rpw, wpg, s);
+        case 6: return dev::launch_u8_mfma_t<6>(in, filt, out, c, h, w, shift, rpw, wpg, s);
+        case 7: return dev::launch_u8_mfma_t<7>(in, filt, out, c, h, w, shift, rpw, wpg, s);
+        case 8: return dev::launch_u8_mfma_t<8>(in, filt, out, c, h, w, shift, rpw, wpg, s);
         default: return hipErrorInvalidValue;
     }
 }

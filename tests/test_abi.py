@@ -154,7 +154,7 @@ def test_tune_table_roundtrip(lib, tmp_path):
 
 def test_u8_variant_entries(lib):
     """uint8 runs on v_dot4 at every radius, on the matrix cores at radii
-    1..4 (the default there) with wave tiles of 16k rows and workgroup tiles
+    1..8 (the default there) with wave tiles of 16k rows and workgroup tiles
     of at most 256 rows; other variants and shapes are refused."""
     pf.tune_reset()
     for r in range(pf.PF_R_MAX + 1):
@@ -170,7 +170,8 @@ def test_u8_variant_entries(lib):
     try:
         pf.tune_set([u8(3, pf.VAR_MFMA, 32, 8), u8(1, pf.VAR_MFMA, 128, 2), u8(4, pf.VAR_DIRECT, 12, 8)])
         assert pf.tune_lookup(pf.KIND_U8, 3, 1 << 22).rows_per_wave == 32
-        for bad in (u8(0, pf.VAR_MFMA, 16, 4), u8(5, pf.VAR_MFMA, 16, 4), u8(3, pf.VAR_MFMA, 24, 1),
+        pf.tune_set([u8(8, pf.VAR_MFMA, 16, 8)])
+        for bad in (u8(0, pf.VAR_MFMA, 16, 4), u8(8, pf.VAR_MFMA, 40, 2), u8(3, pf.VAR_MFMA, 24, 1),
                     u8(3, pf.VAR_MFMA, 64, 8), u8(3, pf.VAR_MFMA, 128, 4), u8(3, pf.VAR_SEPARABLE, 16, 1),
                     u8(3, pf.VAR_SEP_DIRECT, 16, 1)):
             with pytest.raises(pf.PFInvalid):

@@ -137,17 +137,18 @@ def _u8_entries(r, var, by, wpg):
                          us=0.0, context=pf.TUNE_SINGLE) for sc in range(3)]
 
 
+@pytest.mark.parametrize("r", [4, 8])
 @pytest.mark.parametrize("var", [pf.VAR_DIRECT, pf.VAR_MFMA])
-def test_u8_extreme_weights(var):
-    """All-(-128) and all-127 9x9 weights (the largest sums of either sign)
-    on v_dot4 and on the matrix cores."""
+def test_u8_extreme_weights(var, r):
+    """All-(-128) and all-127 weights (the largest sums of either sign) at
+    9x9 and 17x17, on v_dot4 and on the matrix cores."""
     dev = device()
     rng = np.random.default_rng(77)
     try:
-        pf.tune_set(_u8_entries(4, var, 16, 4 if var == pf.VAR_MFMA else 1))
+        pf.tune_set(_u8_entries(r, var, 16, 4 if var == pf.VAR_MFMA else 1))
         for wv in (-128, 127):
             img = rng.integers(0, 256, (1, 40, 300), dtype=np.uint8)
-            f = np.full((9, 9), wv, np.int8)
+            f = np.full((2 * r + 1, 2 * r + 1), wv, np.int8)
             for shift in (0, 13, 31):
                 ref = oracle.filter2d_u8(img, f, shift)
                 got = pf.filter2d_u8(_t(img, dev), _t(f, dev), shift).cpu().numpy()
@@ -243,7 +244,7 @@ MFMA_IMAGES = [(1, 1, 1), (3, 1, 9), (2, 9, 1), (1, 3, 4), (2, 17, 4), (3, 37, 3
                (1, 300, 5), (3, 1080, 1920)]
 
 
-@pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("r", range(1, pf.PF_U8_MFMA_R_MAX + 1))
 def test_u8_mfma_shapes_bit_exact(r):
     dev = device()
     import torch
