@@ -275,6 +275,42 @@ def test_u8_mfma_shapes_bit_exact(r):
         pf.tune_reset()
 
 
+def test_u8_planes_past_2gib():
+    """Nine 16384 x 16384 planes (2.4 GB; the last planes start past 2^31
+    bytes): sampled rows of the first, middle and last planes, edge rows
+    included, against the oracle, on the matrix cores and on v_dot4. A
+    row's reference is the oracle on its 2r+1 clamped input rows, whose
+    middle row needs no clamping there and so equals the full image's."""
+    dev = device()
+    import torch
+    c, h, w, r = 9, 16384, 16384, 3
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(4400)
+    x = torch.randint(0, 256, (c, h, w), dtype=torch.uint8, device=dev, generator=gen)
+    rng = np.random.default_rng(4401)
+    f = rng.integers(-8, 9, (2 * r + 1, 2 * r + 1)).astype(np.int8)
+    fd = _t(f, dev)
+    out = torch.empty_like(x)
+    samples = [(p, y) for p in (0, 4, c - 1) for y in (0, 1, 2, h // 2, h - 2, h - 1)]
+    samples += [(int(p), int(y)) for p, y in zip(rng.integers(0, c, 6), rng.integers(0, h, 6))]
+    try:
+        for var, by, wpg in ((pf.VAR_MFMA, 16, 4), (pf.VAR_DIRECT, 16, 1)):
+            pf.tune_set(_u8_entries(r, var, by, wpg))
+            out.zero_()
+            pf.filter2d_u8(x, fd, 6, out=out)
+            for p, y in samples:
+                rows = [min(max(y + d, 0), h - 1) for d in range(-r, r + 1)]
+                sub = x[p, rows, :].cpu().numpy()[None]
+                ref = oracle.filter2d_u8(sub, f, 6)[0, r]
+                got = out[p, y].cpu().numpy()
+                assert np.array_equal(got, ref), "variant %d plane %d row %d: %d bytes differ" % (
+                    var, p, y, int((got != ref).sum()))
+    finally:
+        pf.tune_reset()
+    del x, out
+    torch.cuda.empty_cache()
+
+
 def test_class_autotune_keeps_results(tmp_path):
     """The class tuner changes only launch shapes and variants: after it (and
     after reloading the table it saved), single-image calls of every kind
