@@ -180,6 +180,40 @@ __device__ __forceinline__ void stage_rows(const uint8_t *__restrict__ plane, ui
     }
 }
 
+// Staging for a tile whose staged columns all lie inside the image (and
+// rows 4-byte aligned): no column clamp, 16 bytes per lane (9 lanes per
+// row, 7 rows per wave pass), loads issued 4 at a time. At 1080p RGB, 7 x 7
+// (all but the edge tiles) 5.7 us against 6.0 us with the 8-byte staging.
+template <int R, class F>
+__device__ __forceinline__ void stage_rows_wide(const uint8_t *__restrict__ plane, uint8_t *rows, int h, int w,
+                                                int x0, int y0, int nrows, int wave, int nwaves, int lane,
+                                                F &&between) {
+    constexpr int G = 16, NL = kMfmaRow / G, PER = kLanes / NL, ST = 4;
+    static_assert(kMfmaRow % G == 0, "whole 16-byte granules per staged row");
+    typedef uint32_t u4a __attribute__((ext_vector_type(4), aligned(4)));
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    const int lr = lane / NL, q = lane - lr * NL;
+    const bool active = lr < PER;
+    const uint32_t xo = (uint32_t)(x0 - kMfmaLeft + G * q);
+    uint8_t *dst = rows + lr * kMfmaRow + G * q;
+    const int step = PER * nwaves;
+    for (int base = PER * wave; base < nrows; base += ST * step) {
+        u4 v[ST];
+#pragma unroll
+        for (int u = 0; u < ST; ++u) {
+            const int ly = min(base + u * step + lr, nrows - 1);
+            const uint32_t roff = (uint32_t)clampi(y0 - R + ly, 0, h - 1) * (uint32_t)w;
+            v[u] = *(const u4a *)(plane + (roff + xo));
+        }
+        if (base == PER * wave) between();
+#pragma unroll
+        for (int u = 0; u < ST; ++u) {
+            const int r0 = base + u * step;
+            if (active && r0 + lr < nrows) *(u4 *)(dst + r0 * kMfmaRow) = v[u] ^ 0x80808080u;
+        }
+    }
+}
+
 // The 4 outputs of a lane's accumulators: arithmetic shift, saturation,
 // packed little-endian.
 __device__ __forceinline__ uint32_t pack_mfma_u8(const v4i &a, int shift) {
@@ -247,7 +281,9 @@ __global__ __launch_bounds__(512) void k_filter_u8_mfma(const uint8_t *__restric
     const int nwaves = nthr / kLanes;
     // The taps' loads are issued while the first rows' loads are in flight.
     auto taps_step = [&]() __attribute__((always_inline)) { stage_taps<R>(filt, taps, tid, nthr); };
-    if (aligned && w >= kMfmaGran)
+    if (aligned && x0 >= kMfmaLeft && x0 + kMfmaRow - kMfmaLeft <= w)
+        stage_rows_wide<R>(in + plane, rows, h, w, x0, y0, nstage, wave, nwaves, lane, taps_step);
+    else if (aligned && w >= kMfmaGran)
         stage_rows<R, true>(in + plane, rows, h, w, x0, y0, nstage, wave, nwaves, lane, taps_step);
     else
         stage_rows<R, false>(in + plane, rows, h, w, x0, y0, nstage, wave, nwaves, lane, taps_step);

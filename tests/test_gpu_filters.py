@@ -237,11 +237,12 @@ def test_u8_group_shapes_bit_exact(r):
 # The matrix-core uint8 kernel: one- to eight-wave workgroups, one to eight
 # 16-row wave tiles per wave, up to the 256-row workgroup tile; images
 # smaller than a tile, ragged in both directions, with rows that are not
-# 4-byte aligned (w not a multiple of 4) and with 4-byte aligned rows whose
-# width is not a multiple of the 16-byte stores.
+# 4-byte aligned (w not a multiple of 4), with 4-byte aligned rows whose
+# width is not a multiple of the 16-byte stores, and with interior tiles
+# (staged without column clamps) beside edge tiles.
 MFMA_SHAPES = [(16, 1), (16, 4), (32, 2), (48, 4), (32, 8), (128, 2)]
 MFMA_IMAGES = [(1, 1, 1), (3, 1, 9), (2, 9, 1), (1, 3, 4), (2, 17, 4), (3, 37, 301), (2, 70, 250), (1, 65, 68),
-               (1, 300, 5), (3, 1080, 1920)]
+               (1, 300, 5), (2, 40, 1000), (3, 1080, 1920)]
 
 
 @pytest.mark.parametrize("r", range(1, pf.PF_U8_MFMA_R_MAX + 1))
