@@ -567,6 +567,29 @@ def main():
                             "workload": "3x1080x1920 uint8 planar, 7x7 int8 weights in -8..8, shift 6, seed 2"}
         log("rgb_u8: %.2f us/call (graph replay, %s), %.2f us/call from Python; v_dot4 kernel %.2f us" % (
             ms * 1e3, result["rgb_u8"]["variant"], ms_host * 1e3, ms_dot4 * 1e3))
+        # Every radius on the same image: the matrix cores (16-row wave
+        # tiles, four waves) against v_dot4 (16-row single-wave tiles), with
+        # seeded int8 weights in -8..8.
+        radii = {}
+        wrng = np.random.default_rng(20)
+        for r in range(1, pf.PF_U8_MFMA_R_MAX + 1):
+            fr = torch.from_numpy(wrng.integers(-8, 9, (2 * r + 1, 2 * r + 1)).astype(np.int8)).to(dev)
+            fn = lambda i, fr=fr: pf.filter2d_u8(xu, fr, cfg.shift, out=ou)  # noqa: E731
+            t = {}
+            for name, var, wpg in (("mfma_us", pf.VAR_MFMA, 4), ("dot4_us", pf.VAR_DIRECT, 1)):
+                pf.tune_set([pf.TuneEntry(kind=pf.KIND_U8, r=r, size_class=2, variant=var, rows_per_wave=16,
+                                          waves_per_group=wpg, us=0.0, context=pf.TUNE_SINGLE)])
+                t[name] = round(graph_ms() * 1e3, 2)
+            radii[str(r)] = t
+        # Back to the table the run uses: the one it loaded, or the one an
+        # autotuning run has written by now (the batch section writes it).
+        pf.tune_reset()
+        table = args.autotune if args.autotune else args.tune
+        if os.path.exists(table):
+            pf.tune_load(table)
+        result["rgb_u8_radii"] = {"unit": "us per call (graph replay), 3x1080x1920 uint8", "by_radius": radii}
+        log("rgb_u8 by radius (matrix cores / v_dot4, us): " + ", ".join(
+            "r%s %.2f/%.2f" % (k, v["mfma_us"], v["dot4_us"]) for k, v in radii.items()))
 
     # ---- serving ------------------------------------------------------------
     if "serve" not in skip and args.serve_seconds > 0:
