@@ -312,7 +312,9 @@ pf_status pf_tune_save(const char *path);
  * whole row chunks of the radius) x (waves_per_group in {1, 2, 4, 8}) shape of
  * single-image calls of every kind, and for
  * PF_KIND_SEP (r <= PF_SEP_DIRECT_R_MAX) also the PF_VAR_SEP_DIRECT variant
- * at the best shape; and the
+ * at the best shape, and for PF_KIND_U8 (r <= PF_U8_MFMA_R_MAX) also the
+ * PF_VAR_MFMA variant at rows_per_wave in {16, 32, 48, 64} x
+ * waves_per_group in {1, 2, 4, 8} within PF_U8_MFMA_TILE_MAX; and the
  * tile heights {8, 16, 32, 64} of the batch kernel on a batch of class
  * images (FP32 kinds). A candidate replaces the default only when at least
  * 3% faster. Installs the winners and writes the table to `path` if it is
