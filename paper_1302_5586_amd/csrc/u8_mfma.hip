@@ -50,7 +50,7 @@ constexpr int kMfmaBlocks = 8;
 constexpr int kMfmaTileW = kMfmaN * kMfmaBlocks;  // output columns of a workgroup tile
 constexpr int kMfmaLeft = 8;                  // staged columns left of the tile
 constexpr int kMfmaRow = kMfmaTileW + 16;     // LDS bytes per staged row: columns x0 - 8 .. x0 + W + 7
-constexpr int kMfmaGran = kMfmaBlocks == 8 ? 8 : 4;  // bytes a lane stages per row
+constexpr int kMfmaGran = 8;                  // bytes a lane stages per row (edge tiles)
 constexpr int kMfmaFill = kMfmaRow / kMfmaGran;  // lanes per staged row: every byte of it
 constexpr int kMfmaStage = 8;                 // staged loads a thread has in flight at once
 static_assert(kMfmaRow % kMfmaGran == 0, "whole granules per staged row");
@@ -145,17 +145,12 @@ __device__ __forceinline__ void stage_rows(const uint8_t *__restrict__ plane, ui
             const int ly = min(base + u * step + lr, nrows - 1);
             const uint32_t roff = (uint32_t)clampi(y0 - R + ly, 0, h - 1) * (uint32_t)w;
             if constexpr (ALIGNED) {
-                if constexpr (ND == 1) {
-                    const uint32_t d = *(const uint32_t *)(plane + (roff + xo[0]));
-                    v[u][0] = __builtin_amdgcn_perm(d, d, sel[0]);
-                } else {
-                    // 8 bytes: selector values 0..3 pick bytes of the first
-                    // dword, 4..7 bytes of the second.
-                    typedef uint32_t u2 __attribute__((ext_vector_type(2), aligned(4)));
-                    const u2 d = *(const u2 *)(plane + (roff + xo[0]));
+                // Selector values 0..3 pick bytes of the first dword, 4..7
+                // bytes of the second.
+                typedef uint32_t u2 __attribute__((ext_vector_type(2), aligned(4)));
+                const u2 d = *(const u2 *)(plane + (roff + xo[0]));
 #pragma unroll
-                    for (int j = 0; j < ND; ++j) v[u][j] = __builtin_amdgcn_perm(d[1], d[0], sel[j]);
-                }
+                for (int j = 0; j < ND; ++j) v[u][j] = __builtin_amdgcn_perm(d[1], d[0], sel[j]);
             } else {
 #pragma unroll
                 for (int j = 0; j < ND; ++j) {
