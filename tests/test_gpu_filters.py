@@ -180,6 +180,39 @@ def test_determinism_and_nan():
     assert not np.isnan(a[0, 0])
 
 
+def test_calls_on_a_side_stream():
+    """The single-image calls run on the stream they are given: inputs copied
+    from pinned host memory and scaled on a side stream, then filtered on it
+    with nothing synchronising the default stream, match the oracle (FP32 2D
+    and separable, uint8 on the matrix cores)."""
+    dev = device()
+    import torch
+    rng = np.random.default_rng(4500)
+    img = rng.random((300, 500), dtype=np.float32)
+    f = _rand_filter(rng, 2)
+    fx = rng.random(5).astype(np.float32)
+    fy = rng.random(5).astype(np.float32)
+    u = rng.integers(0, 128, (3, 200, 300), dtype=np.uint8)
+    f8 = rng.integers(-8, 9, (7, 7)).astype(np.int8)
+    hx = torch.from_numpy(img).pin_memory()
+    hu = torch.from_numpy(u).pin_memory()
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        x = hx.to(dev, non_blocking=True) * 2.0
+        xu = hu.to(dev, non_blocking=True) * 2
+        fd, fxd, fyd, f8d = (torch.from_numpy(a).to(dev, non_blocking=False) for a in (f, fx, fy, f8))
+        o2 = pf.filter2d(x, fd, stream=side)
+        osep = pf.filter_sep(x, fxd, fyd, stream=side)
+        ou = pf.filter2d_u8(xu, f8d, 6, stream=side)
+    side.synchronize()
+    img2 = img * np.float32(2.0)
+    assert_close(o2.cpu().numpy(), oracle.filter2d_f32(img2, f), tolerance_2d(img2, f, 2), "2d on a side stream")
+    assert_close(osep.cpu().numpy(), oracle.filter_sep_f32(img2, fx, fy), tolerance_sep(img2, fx, fy),
+                 "sep on a side stream")
+    assert np.array_equal(ou.cpu().numpy(), oracle.filter2d_u8(u * 2, f8, 6))
+
+
 def test_strided_views_rejected():
     dev = device()
     import torch
