@@ -213,6 +213,37 @@ def test_calls_on_a_side_stream():
     assert np.array_equal(ou.cpu().numpy(), oracle.filter2d_u8(u * 2, f8, 6))
 
 
+def test_u8_graph_replays():
+    """The uint8 call captured in a graph (as the benchmark times it) and
+    replayed four times, with the input rewritten eagerly between replays:
+    every replay's output is bit-exact against the oracle for the input it
+    read."""
+    dev = device()
+    import torch
+    rng = np.random.default_rng(4600)
+    imgs = [rng.integers(0, 256, (3, 120, 400), dtype=np.uint8) for _ in range(4)]
+    f8 = rng.integers(-8, 9, (7, 7)).astype(np.int8)
+    x = _t(imgs[0], dev)
+    fd = _t(f8, dev)
+    out = torch.empty_like(x)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        pf.filter2d_u8(x, fd, 6, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pf.filter2d_u8(x, fd, 6, out=out)
+    for img in imgs:
+        x.copy_(torch.from_numpy(img).to(dev))
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), oracle.filter2d_u8(img, f8, 6))
+    del g
+
+
 def test_strided_views_rejected():
     dev = device()
     import torch
